@@ -1,0 +1,254 @@
+#!/usr/bin/env python3
+"""Benchmark of the five-point Jacobi hot path on one MI355X.
+
+One step = one call of the plain FP64 method on the 4096x4096 grid
+(N(0,1), seed 0) with T sweeps (default 100): ring setup, T sweep kernels with
+the ping-pong swap, result in `out`. Inputs are resident in HBM before the
+timed region. The printed value is the whole-job effective bandwidth,
+16 B per interior point per sweep (8 B read + 8 B written, compulsory),
+divided by the wall time of the timed steps.
+
+Also reported on the same JSON line:
+  roofline      the sweep kernel's algorithmic bytes per launch divided by its
+                average launch duration (HIP events on the launch stream),
+                against the 8 TB/s HBM peak; `traffic` from rocprofv3 counters
+                when a committed measurement of the current kernel source exists
+  cpu_baseline  the CPU oracle (C + OpenMP twin) timed on the host's cores on
+                a bounded sample of the same workload
+  extensions    the other forms of the hot path (when built)
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--sweeps T]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "hot-path GB/s or FLOP/s and % roofline, plain FP64 vs mixed/batched at stated tol"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_f64_4096_traffic.json")
+SWEEP_SRC = os.path.join(ROOT, "paper_2512_19851_amd", "csrc", "sweep.hip")
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def source_sha(path: str) -> str:
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(launch_bytes: float):
+    """HBM bytes per launch from committed rocprofv3 counters, if they match this source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        rec = json.load(f)
+    if rec.get("source_sha") != source_sha(SWEEP_SRC):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def time_kernel_launches(ops, a, b, reps: int) -> float:
+    """Average duration (ms) of one sweep launch over `reps` back-to-back launches.
+
+    One HIP event pair on the launch stream brackets the launches, so the
+    figure is kernel time plus the (small) dispatch gaps between them.
+    """
+    import torch
+
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        ops.sweep(a, b)
+        a, b = b, a
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        ops.sweep(a, b)
+        a, b = b, a
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def cpu_baseline(u0_np, T_step: int, budget_s: float):
+    """Time the CPU oracle (C + OpenMP) on a bounded number of sweeps of the same grid."""
+    from oracle import cref
+
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(16, os.cpu_count() or 1)
+    used = cref.threads(nthreads)
+    H, W = u0_np.shape
+    cref.jacobi5(u0_np, 1, nthreads=nthreads)  # first touch, thread start-up
+    t0 = time.perf_counter()
+    cref.jacobi5(u0_np, 10, nthreads=nthreads)
+    per = max((time.perf_counter() - t0) / 10, 1e-5)
+    sweeps = int(max(10, min(50 * T_step, budget_s / per)))
+    t0 = time.perf_counter()
+    cref.jacobi5(u0_np, sweeps, nthreads=nthreads)
+    dt = time.perf_counter() - t0
+    gbs = 16.0 * (H - 2) * (W - 2) * sweeps / dt / 1e9
+    return {
+        "value": round(gbs, 3),
+        "unit": "GB/s",
+        "cores": used,
+        "kind": "oracle",
+        "sample": f"{H}x{W} FP64 N(0,1) seed 0, {sweeps} sweeps in {dt:.1f} s "
+                  f"(C + OpenMP oracle, {used} threads); same 16 B/point/sweep accounting",
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--sweeps", type=int, default=100, help="sweeps T per step")
+    ap.add_argument("--n", type=int, default=4096, help="grid side")
+    ap.add_argument("--kernel-reps", type=int, default=100)
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of CPU oracle work")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extensions", action="store_true")
+    ap.add_argument("--mode", choices=["step", "sweep", "copy"], default="step",
+                    help="step: the benchmark; sweep: only --kernel-reps sweep launches; "
+                         "copy: only --kernel-reps plain grid copies (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the library has no multi-GPU path; "
+              "run with --gpus 1", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2512_19851_amd import ops
+    from workloads import large_f64
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n, T = args.n, args.sweeps
+    log(f"[bench] generating {n}x{n} FP64 N(0,1) seed 0")
+    u0_np = large_f64(0, n)
+    u0 = torch.from_numpy(u0_np).to(dev)
+    out = torch.empty_like(u0)
+    work = torch.empty_like(u0)
+    interior = (n - 2) * (n - 2)
+    launch_bytes = 16.0 * interior
+    step_bytes = launch_bytes * T
+
+    if args.mode != "step":
+        # short runs for rocprofv3 counter passes: no CPU work, no extensions
+        a = u0.clone()
+        b = u0.clone()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.kernel_reps):
+            if args.mode == "sweep":
+                ops.sweep(a, b)
+            else:
+                ops.jacobi5(a, 0, out=b)  # T = 0: one plain copy of the grid
+            a, b = b, a
+        e1.record()
+        torch.cuda.synchronize()
+        per = e0.elapsed_time(e1) / args.kernel_reps
+        moved = launch_bytes if args.mode == "sweep" else 16.0 * n * n
+        print(json.dumps({"mode": args.mode, "launches": args.kernel_reps, "avg_us": round(per * 1e3, 2),
+                          "algorithmic_bytes_per_launch": moved,
+                          "GBps": round(moved / (per * 1e-3) / 1e9, 1)}), flush=True)
+        return 0
+
+    log(f"[bench] warmup {args.warmup} steps of T={T}")
+    for _ in range(args.warmup):
+        ops.jacobi5(u0, T, out=out, work=work)
+    torch.cuda.synchronize()
+
+    log(f"[bench] timing {args.steps} steps")
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        ops.jacobi5(u0, T, out=out, work=work)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = ev0.elapsed_time(ev1)
+    sec_per_step = wall / args.steps
+    value = step_bytes / sec_per_step / 1e9
+    log(f"[bench] {sec_per_step * 1e3:.3f} ms/step, {value:.1f} GB/s (events: {ev_ms / args.steps:.3f} ms/step)")
+
+    log(f"[bench] per-launch kernel timing, {args.kernel_reps} launches")
+    a = out.clone()
+    b = work
+    b.copy_(a)
+    avg_ms = time_kernel_launches(ops, a, b, args.kernel_reps)
+    achieved = launch_bytes / (avg_ms * 1e-3) / 1e9
+    traffic = load_traffic(launch_bytes)
+    roofline = {
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "kernel": "sweep_kernel<double,2,8> (one sweep of the 4096x4096 FP64 grid)",
+        "algorithmic_bytes_per_launch": launch_bytes,
+        "avg_launch_us": round(avg_ms * 1e3, 2),
+        "step_us_per_sweep": round(sec_per_step / T * 1e6, 2),
+    }
+
+    rec = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec_per_step * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"plain FP64 five-point Jacobi, {n}x{n} grid N(0,1) seed 0, {T} sweeps per step",
+            "grid": [n, n],
+            "sweeps_per_step": T,
+            "bytes_per_point_per_sweep": 16,
+            "parallelism": "single GPU",
+        },
+        "roofline": roofline,
+    }
+
+    if not args.no_extensions:
+        rec["extensions"] = {}
+
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline")
+        rec["cpu_baseline"] = cpu_baseline(u0_np, T, args.cpu_budget)
+    else:
+        rec["cpu_baseline"] = None
+
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,14 @@
+"""MI355X (gfx950) library for the 2-D five-point Jacobi (Laplace) sweep.
+
+The computation is the hot path of the stencil abstraction in "An Adaptive
+Distributed Stencil Abstraction for GPUs" (listing of the 2-D Laplace solver,
+Section III-A; benchmarks of Section V). All arithmetic runs in the HIP
+kernels of ``libsten.so`` (C ABI in ``include/sten.h``); this package only
+marshals arguments. There is no CPU fallback: loading fails loudly when the
+library is missing.
+"""
+
+from ._lib import StenError, load  # noqa: F401
+from .ops import jacobi5, set_sweep_rows, sweep  # noqa: F401
+
+__all__ = ["StenError", "load", "jacobi5", "set_sweep_rows", "sweep"]

@@ -1,0 +1,119 @@
+"""ctypes loader for libsten.so: argument marshalling only.
+
+torch is imported before the library is loaded so that libsten's HIP runtime
+dependency resolves to the runtime torch already mapped; a second HIP runtime
+in the process would not understand torch's stream handles. The loader checks
+that exactly one HIP runtime is mapped and fails loudly otherwise, and fails
+loudly when the library has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (must precede loading libsten; see module docstring)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsten.so")
+
+STATUS = {
+    0: "STEN_OK",
+    -1: "STEN_ERR_ARG",
+    -2: "STEN_ERR_ALIAS",
+    -3: "STEN_ERR_PTR",
+    -4: "STEN_ERR_WORKSPACE",
+    -5: "STEN_ERR_HIP",
+    -6: "STEN_ERR_UNSUPPORTED",
+}
+
+
+class StenError(RuntimeError):
+    """A libsten call returned a non-zero status."""
+
+    def __init__(self, fn: str, code: int, hip: int | None = None):
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+        msg = f"{fn} failed: {self.name}"
+        if hip:
+            msg += f" (hipError {hip})"
+        super().__init__(msg)
+
+
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_u32 = ctypes.c_uint32
+_vp = ctypes.c_void_p
+_sz = ctypes.c_size_t
+_f64 = ctypes.c_double
+_f32 = ctypes.c_float
+
+# name -> (restype, argtypes); mirrors include/sten.h
+SIGNATURES = {
+    "sten_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "sten_last_hip_error": (ctypes.c_int, []),
+    "sten_version": (ctypes.c_char_p, []),
+    "sten_xcd_tile_of_block": (_u32, [_u32, _u32]),
+    "sten_jacobi5_f64": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, _i64, _i32, _f64, _vp]),
+    "sten_jacobi5_f32": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, _i64, _i32, _f32, _vp]),
+    "sten_tune_sweep_rows": (ctypes.c_int, [_i32]),
+    "sten_sweep_f64": (ctypes.c_int, [_vp, _vp, _i64, _i64, _i64, _f64, _vp]),
+    "sten_sweep_f32": (ctypes.c_int, [_vp, _vp, _i64, _i64, _i64, _f32, _vp]),
+}
+
+_lib = None
+
+
+def _hip_runtimes_mapped() -> list[str]:
+    try:
+        with open("/proc/self/maps") as f:
+            paths = {line.split()[-1] for line in f if "libamdhip64" in line}
+    except OSError:
+        return []
+    return sorted(paths)
+
+
+def load():
+    """Load libsten.so once; raise if it is missing or a second HIP runtime appears."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
+            "(there is no CPU fallback)"
+        )
+    lib = ctypes.CDLL(LIB_PATH)
+    runtimes = _hip_runtimes_mapped()
+    if len(runtimes) > 1:
+        raise RuntimeError(f"two HIP runtimes are mapped ({runtimes}); import torch before libsten")
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def declare(name: str, restype, argtypes) -> None:
+    """Register the ctypes signature of a further entry point."""
+    SIGNATURES[name] = (restype, argtypes)
+    if _lib is not None:
+        fn = getattr(_lib, name)
+        fn.restype = restype
+        fn.argtypes = argtypes
+
+
+def check(fn_name: str, code: int) -> None:
+    if code != 0:
+        hip = load().sten_last_hip_error() if code == -5 else None
+        raise StenError(fn_name, code, hip)
+
+
+def call(fn_name: str, *args) -> None:
+    """Call an entry point and raise StenError on a non-zero status."""
+    check(fn_name, getattr(load(), fn_name)(*args))
+
+
+def exported_symbols() -> list[str]:
+    return list(SIGNATURES)

@@ -1,0 +1,298 @@
+// Plain five-point Jacobi sweep (listing of the 2-D Laplace solver,
+// Section III-A): out[i,j] = c * (((in[i-1,j] + in[i+1,j]) + in[i,j-1]) + in[i,j+1])
+// on the interior, iterated T times with a ping-pong swap.
+//
+// Kernel design (gfx950, HBM-bound: 4 flop per 16 B in FP64):
+//  * A workgroup of 256 lanes (4 waves) owns a tile of ROWS output rows by
+//    256*V columns. Each lane owns V consecutive columns (one 16-byte vector:
+//    2 doubles or 4 floats), so every row load of a wave is a coalesced 1 KiB
+//    global_load_dwordx4.
+//  * The lane loads its column vector for all ROWS+2 input rows up front
+//    (ROWS+2 independent 16-byte loads in flight per lane), then walks down:
+//    up/down neighbours come from the lane's own registers, left/right
+//    neighbours of the vector's end elements from the adjacent lanes through a
+//    cross-lane shuffle; only the wave's two edge lanes issue one extra scalar
+//    load per row. Each input element is read from HBM once per tile; the two
+//    halo rows are shared with the vertically adjacent tiles through L2.
+//  * Tiles are mapped to workgroups so that each XCD walks a contiguous band
+//    of rows, keeping halo rows in that XCD's L2.
+//  * The arithmetic is exactly the listing's order with one rounding per
+//    operation; the library is built with -ffp-contract=off.
+#include <algorithm>
+
+#include "common.hpp"
+
+namespace sten {
+namespace {
+
+constexpr int kBlock = 256;
+
+template <typename T, int V>
+struct Vec;
+template <typename T>
+struct Vec<T, 1> {
+    typedef T type;
+};
+template <>
+struct Vec<double, 2> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Vec<float, 4> {
+    typedef float type __attribute__((ext_vector_type(4)));
+};
+
+// Load columns [jb, jb+V) of one row; columns at or beyond W read as 0.
+template <typename T, int V>
+__device__ __forceinline__ void load_vec(const T* __restrict__ row, int jb, int W, T (&v)[V]) {
+    if constexpr (V == 1) {
+        v[0] = (jb < W) ? row[jb] : T(0);
+    } else {
+        if (jb + V <= W) {
+            typedef typename Vec<T, V>::type VT;
+            VT x = *reinterpret_cast<const VT*>(row + jb);
+#pragma unroll
+            for (int e = 0; e < V; ++e) v[e] = x[e];
+        } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e) v[e] = (jb + e < W) ? row[jb + e] : T(0);
+        }
+    }
+}
+
+// Store columns [jb, jb+V) of one row, skipping the ring columns 0 and W-1
+// and anything at or beyond W.
+template <typename T, int V>
+__device__ __forceinline__ void store_vec(T* __restrict__ row, int jb, int W, const T (&v)[V]) {
+    if constexpr (V > 1) {
+        if (jb >= 1 && jb + V <= W - 1) {
+            typedef typename Vec<T, V>::type VT;
+            VT x;
+#pragma unroll
+            for (int e = 0; e < V; ++e) x[e] = v[e];
+            *reinterpret_cast<VT*>(row + jb) = x;
+            return;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+        int j = jb + e;
+        if (j >= 1 && j <= W - 2) row[j] = v[e];
+    }
+}
+
+// One tile of the sweep. FULL: the tile has ROWS output rows and every lane of
+// the wave lies inside the grid (jb + V <= W), so loads need no guards.
+template <typename T, int V, int ROWS, bool FULL>
+__device__ __forceinline__ void sweep_tile(const T* __restrict__ src, T* __restrict__ dst, int n, int jb,
+                                           int lane, int W, int64_t ld, T c) {
+    T r[ROWS + 2][V];
+#pragma unroll
+    for (int k = 0; k < ROWS + 2; ++k) {
+        if (FULL) {
+            typedef typename Vec<T, V>::type VT;
+            if constexpr (V == 1) {
+                r[k][0] = src[(int64_t)k * ld + jb];
+            } else {
+                VT x = *reinterpret_cast<const VT*>(src + (int64_t)k * ld + jb);
+#pragma unroll
+                for (int e = 0; e < V; ++e) r[k][e] = x[e];
+            }
+        } else if (k < n + 2) {
+            load_vec<T, V>(src + (int64_t)k * ld, jb, W, r[k]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e) r[k][e] = T(0);
+        }
+    }
+    // The wave's edge lanes fetch the one neighbour that lies in another wave.
+    T el[ROWS], er[ROWS];
+#pragma unroll
+    for (int k = 0; k < ROWS; ++k) {
+        el[k] = T(0);
+        er[k] = T(0);
+        if (FULL || k < n) {
+            const T* row = src + (int64_t)(k + 1) * ld;
+            if (lane == 0 && jb > 0 && jb <= W) el[k] = row[jb - 1];
+            if (lane == kWave - 1 && jb + V < W) er[k] = row[jb + V];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < ROWS; ++k) {
+        if (FULL || k < n) {  // n is uniform over the block, so whole waves shuffle together
+            T left0 = __shfl_up(r[k + 1][V - 1], 1);
+            T rightv = __shfl_down(r[k + 1][0], 1);
+            if (lane == 0) left0 = el[k];
+            if (lane == kWave - 1) rightv = er[k];
+            T o[V];
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const T west = (e == 0) ? left0 : r[k + 1][e > 0 ? e - 1 : 0];
+                const T east = (e == V - 1) ? rightv : r[k + 1][e < V - 1 ? e + 1 : 0];
+                T s = r[k][e] + r[k + 2][e];  // N + S
+                s = s + west;                 // + W
+                s = s + east;                 // + E
+                o[e] = c * s;
+            }
+            store_vec<T, V>(dst + (int64_t)k * ld, jb, W, o);
+        }
+    }
+}
+
+template <typename T, int V, int ROWS>
+__global__ __launch_bounds__(kBlock) void sweep_kernel(const T* __restrict__ in, T* __restrict__ out,
+                                                       int H, int W, int64_t ld, T c, uint32_t tiles_x) {
+    const uint32_t tile = xcd_tile_of_block(blockIdx.x, gridDim.x);
+    const uint32_t ty = tile / tiles_x;
+    const uint32_t tx = tile - ty * tiles_x;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int jb = ((int)tx * kBlock + (int)threadIdx.x) * V;
+    const int i0 = 1 + (int)ty * ROWS;       // first output row of the tile
+    const int n = min(ROWS, H - 1 - i0);     // output rows in the tile, >= 1 (same for the whole block)
+    const int wave_end = (jb - lane * V) + kWave * V;  // one past the wave's last column
+    const T* src = in + (int64_t)(i0 - 1) * ld;
+    T* dst = out + (int64_t)i0 * ld;
+    if (n == ROWS && wave_end <= W)
+        sweep_tile<T, V, ROWS, true>(src, dst, n, jb, lane, W, ld, c);
+    else
+        sweep_tile<T, V, ROWS, false>(src, dst, n, jb, lane, W, ld, c);
+}
+
+// Copy the boundary ring of u0 into d1 and (when not NULL) d2. Needs H, W >= 2.
+template <typename T>
+__global__ void ring_copy_kernel(const T* __restrict__ u0, T* __restrict__ d1, T* __restrict__ d2,
+                                 int H, int W, int64_t ld) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nring = 2 * (int64_t)W + 2 * (int64_t)(H - 2);
+    if (idx >= nring) return;
+    int i, j;
+    if (idx < W) {
+        i = 0;
+        j = (int)idx;
+    } else if (idx < 2 * (int64_t)W) {
+        i = H - 1;
+        j = (int)(idx - W);
+    } else {
+        const int64_t r = idx - 2 * (int64_t)W;
+        i = 1 + (int)(r >> 1);
+        j = (r & 1) ? W - 1 : 0;
+    }
+    const int64_t off = (int64_t)i * ld + j;
+    const T v = u0[off];
+    d1[off] = v;
+    if (d2 != nullptr) d2[off] = v;
+}
+
+// Plain 2-D copy of an H x W grid (degenerate calls: T = 0 or empty interior).
+template <typename T>
+__global__ void copy_kernel(const T* __restrict__ src, T* __restrict__ dst, int H, int W, int64_t ld) {
+    const int64_t total = (int64_t)H * W;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx / W;
+        const int64_t j = idx - i * W;
+        dst[i * ld + j] = src[i * ld + j];
+    }
+}
+
+int g_rows_override = 0;  // 0: built-in choice; else rows per tile (tuning hook)
+
+template <typename T, int V, int ROWS>
+void launch_sweep_rows(const T* in, T* out, int H, int W, int64_t ld, T c, hipStream_t s) {
+    const uint32_t tiles_x = ceil_div(W, (int64_t)kBlock * V);
+    const uint32_t tiles_y = ceil_div(H - 2, ROWS);
+    sweep_kernel<T, V, ROWS><<<tiles_x * tiles_y, kBlock, 0, s>>>(in, out, H, W, ld, c, tiles_x);
+}
+
+template <typename T, int V>
+void launch_sweep(const T* in, T* out, int H, int W, int64_t ld, T c, int rows, hipStream_t s) {
+    switch (rows) {
+        case 4: launch_sweep_rows<T, V, 4>(in, out, H, W, ld, c, s); break;
+        case 16: launch_sweep_rows<T, V, 16>(in, out, H, W, ld, c, s); break;
+        default: launch_sweep_rows<T, V, 8>(in, out, H, W, ld, c, s); break;
+    }
+}
+
+template <typename T>
+sten_status run_jacobi5(const T* u0, T* out, T* work, int64_t H, int64_t W, int64_t ld, int32_t T_,
+                        T c, hipStream_t stream) {
+    const bool interior = H >= 3 && W >= 3;
+    const bool need_work = interior && T_ >= 2;
+    sten_status st = check_grid_args(u0, out, work, need_work, H, W, ld, T_, sizeof(T));
+    if (st != STEN_OK || H == 0 || W == 0) return st;
+    const int h = (int)H, w = (int)W;
+    if (!interior || T_ == 0) {
+        const int64_t total = H * W;
+        const uint32_t blocks = (uint32_t)std::min<int64_t>((total + 255) / 256, 65536);
+        copy_kernel<T><<<blocks, 256, 0, stream>>>(u0, out, h, w, ld);
+        return check_launch();
+    }
+    {
+        const int64_t nring = 2 * W + 2 * (H - 2);
+        ring_copy_kernel<T><<<ceil_div(nring, 256), 256, 0, stream>>>(u0, out, need_work ? work : nullptr,
+                                                                       h, w, ld);
+    }
+    constexpr int VV = 16 / (int)sizeof(T);
+    const uintptr_t align_bits = (uintptr_t)u0 | (uintptr_t)out | (need_work ? (uintptr_t)work : 0);
+    const bool vec_ok = (align_bits % 16 == 0) && (ld % VV == 0);
+    const int rows = g_rows_override > 0 ? g_rows_override : (sizeof(T) == 8 ? 8 : 8);
+    const T* src = u0;
+    for (int32_t k = 1; k <= T_; ++k) {
+        T* dst = ((T_ - k) % 2 == 0) ? out : work;
+        if (vec_ok)
+            launch_sweep<T, VV>(src, dst, h, w, ld, c, rows, stream);
+        else
+            launch_sweep<T, 1>(src, dst, h, w, ld, c, rows, stream);
+        src = dst;
+    }
+    return check_launch();
+}
+
+template <typename T>
+sten_status run_sweep_once(const T* src, T* dst, int64_t H, int64_t W, int64_t ld, T c, hipStream_t stream) {
+    sten_status st = check_grid_args(src, dst, nullptr, false, H, W, ld, 1, sizeof(T));
+    if (st != STEN_OK || H < 3 || W < 3) return st;
+    constexpr int VV = 16 / (int)sizeof(T);
+    const bool vec_ok = (((uintptr_t)src | (uintptr_t)dst) % 16 == 0) && (ld % VV == 0);
+    const int rows = g_rows_override > 0 ? g_rows_override : 8;
+    if (vec_ok)
+        launch_sweep<T, VV>(src, dst, (int)H, (int)W, ld, c, rows, stream);
+    else
+        launch_sweep<T, 1>(src, dst, (int)H, (int)W, ld, c, rows, stream);
+    return check_launch();
+}
+
+}  // namespace
+}  // namespace sten
+
+extern "C" {
+
+sten_status sten_sweep_f64(const double* src, double* dst, int64_t H, int64_t W, int64_t ld, double c,
+                           hipStream_t stream) {
+    return sten::run_sweep_once<double>(src, dst, H, W, ld, c, stream);
+}
+
+sten_status sten_sweep_f32(const float* src, float* dst, int64_t H, int64_t W, int64_t ld, float c,
+                           hipStream_t stream) {
+    return sten::run_sweep_once<float>(src, dst, H, W, ld, c, stream);
+}
+
+sten_status sten_jacobi5_f64(const double* u0, double* out, double* work, int64_t H, int64_t W, int64_t ld,
+                             int32_t T, double c, hipStream_t stream) {
+    return sten::run_jacobi5<double>(u0, out, work, H, W, ld, T, c, stream);
+}
+
+sten_status sten_jacobi5_f32(const float* u0, float* out, float* work, int64_t H, int64_t W, int64_t ld,
+                             int32_t T, float c, hipStream_t stream) {
+    return sten::run_jacobi5<float>(u0, out, work, H, W, ld, T, c, stream);
+}
+
+// Tuning hook: rows per tile of the sweep kernels (4, 8 or 16; 0 restores the
+// built-in choice). Returns STEN_ERR_ARG for other values.
+sten_status sten_tune_sweep_rows(int32_t rows) {
+    if (rows != 0 && rows != 4 && rows != 8 && rows != 16) return STEN_ERR_ARG;
+    sten::g_rows_override = rows;
+    return STEN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+"""libsten loads without a GPU and exports every symbol include/sten.h declares.
+
+No compute call is made here; only host-side helpers are exercised.
+"""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sten.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:[A-Za-z_][\w\s\*]*?)\b(sten_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2512_19851_amd import _lib
+
+    return _lib.load()
+
+
+def test_header_declares_functions():
+    names = declared_functions()
+    assert "sten_jacobi5_f64" in names and "sten_status_string" in names
+    assert len(names) >= 8
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, f"declared but not exported: {missing}"
+
+
+def test_binding_covers_header():
+    from paper_2512_19851_amd import _lib
+
+    missing = [n for n in declared_functions() if n not in _lib.SIGNATURES]
+    assert not missing, f"no ctypes signature for: {missing}"
+
+
+def test_single_hip_runtime(lib):
+    from paper_2512_19851_amd import _lib
+
+    assert len(_lib._hip_runtimes_mapped()) <= 1
+
+
+def test_status_strings(lib):
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        s = lib.sten_status_string(code).decode()
+        assert s.startswith("STEN_")
+    assert b"gfx950" in lib.sten_version()
+
+
+@pytest.mark.parametrize("nb", [1, 2, 7, 8, 9, 15, 16, 17, 255, 256, 1000, 1024, 2047, 8191])
+def test_xcd_map_is_bijective_and_banded(lib, nb):
+    tiles = [lib.sten_xcd_tile_of_block(b, nb) for b in range(nb)]
+    assert sorted(tiles) == list(range(nb))
+    # every XCD (b mod 8) walks a contiguous, increasing range of tiles
+    for x in range(8):
+        mine = [tiles[b] for b in range(x, nb, 8)]
+        assert mine == list(range(mine[0], mine[0] + len(mine))) if mine else True
+
+
+def test_tune_hook_rejects_bad_rows(lib):
+    assert lib.sten_tune_sweep_rows(5) == -1
+    assert lib.sten_tune_sweep_rows(0) == 0
+
+
+def test_validation_before_any_hip_call(lib):
+    """Argument errors are reported without touching the GPU (no device here)."""
+    f = lib.sten_jacobi5_f64
+    assert f(None, None, None, -1, 4, 4, 1, 0.25, None) == -1     # H < 0
+    assert f(None, None, None, 4, 4, 3, 1, 0.25, None) == -1      # ld < W
+    assert f(None, None, None, 4, 4, 4, -2, 0.25, None) == -1     # T < 0
+    assert f(None, None, None, 0, 4, 4, 1, 0.25, None) == 0       # empty grid: no-op
+    assert f(None, None, None, 4, 4, 4, 1, 0.25, None) == -3      # NULL pointers
+    # overlapping buffers are rejected before any pointer query
+    assert f(4096, 4096 + 8, 1 << 20, 4, 4, 4, 1, 0.25, None) == -2
+    assert f(4096, 1 << 20, 1 << 20, 4, 4, 4, 2, 0.25, None) == -2
