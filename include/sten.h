@@ -100,6 +100,65 @@ sten_status sten_sweep_f32(const float* src, float* dst, int64_t H, int64_t W, i
 sten_status sten_tune_sweep_rows(int32_t rows);
 
 /* ------------------------------------------------------------------------ */
+/* Reduced-precision form: hi/lo encoding (extension; not in the paper)     */
+/* ------------------------------------------------------------------------ */
+/*
+ * An FP64 grid x is stored as an FP32 plane hi = RN32(x) and an int16 plane
+ * q with x ~= hi + q * delta(hi), delta(hi) = ulp32(hi) * 2^-16 (floored at
+ * 2^-149): 6 bytes per point instead of 8, |x - decoded| <= 2^-40 |x|.
+ * Layout of one encoded grid in a caller buffer `hilo` (256-byte aligned):
+ * bytes [0, H*ld*4) hold the hi plane (row stride ld floats), followed, at
+ * the next multiple of 256 bytes, by the q plane (row stride ld int16).
+ * Each sweep decodes its inputs to FP32 pairs, sums them with error-free
+ * FP32 transformations (double-word sums), multiplies by c as a double-word
+ * product and re-encodes the result; FP64 is used only to encode and decode.
+ */
+
+/* Bytes of one encoded H x ld grid (hi plane + q plane, with alignment). */
+size_t sten_hilo_bytes(int64_t H, int64_t ld);
+
+/* Encode an FP64 grid. |x| must stay below the FP32 range (else the hi plane
+ * holds inf). Bit-exact with the FP64 definition above (the one q value int16
+ * cannot hold, +32768, is renormalised by stepping hi to the next FP32 value). */
+sten_status sten_hilo_encode(const double* x, void* hilo, int64_t H, int64_t W, int64_t ld,
+                             hipStream_t stream);
+
+/* Decode to FP64 (exact: hi + q * delta is representable in FP64). */
+sten_status sten_hilo_decode(const void* hilo, double* x, int64_t H, int64_t W, int64_t ld,
+                             hipStream_t stream);
+
+/*
+ * T sweeps on encoded grids: src (never written) -> dst, with `work` as the
+ * second ping-pong grid (needed when T >= 2). All three are encoded grids of
+ * sten_hilo_bytes(H, ld) bytes each. The ring of dst (and work) is set from
+ * src. Componentwise error vs the FP64 method on decode(src), J the T-sweep
+ * map: |err| <= (T 2^-40 (1 + 2^-22) + T a)(1 + 2^-39)^T (|J| |x|), with
+ * a = 17 * 2^-48 when c is a power of two and 20 * 2^-48 otherwise.
+ */
+sten_status sten_jacobi5_hilo(const void* src, void* dst, void* work,
+                              int64_t H, int64_t W, int64_t ld, int32_t T, double c,
+                              hipStream_t stream);
+
+/* Bytes of `work` for sten_jacobi5_f64_hilo: two encoded grids. */
+size_t sten_jacobi5_f64_hilo_work_bytes(int64_t H, int64_t ld);
+
+/*
+ * FP64 in, FP64 out through the hi/lo form: encode u0, T encoded sweeps,
+ * decode into out. The ring of out is copied from u0 exactly; the interior
+ * obeys the bound of sten_jacobi5_hilo (for T = 0 the interior is
+ * decode(encode(u0)), within 2^-40 |u0|). work_bytes must be at least
+ * sten_jacobi5_f64_hilo_work_bytes(H, ld) (else STEN_ERR_WORKSPACE); work
+ * must be 256-byte aligned (else STEN_ERR_ARG).
+ */
+sten_status sten_jacobi5_f64_hilo(const double* u0, double* out, void* work, size_t work_bytes,
+                                  int64_t H, int64_t W, int64_t ld, int32_t T, double c,
+                                  hipStream_t stream);
+
+/* Tuning hook: output rows per workgroup tile of the hi/lo sweep kernel (4 or
+ * 8; 0 restores the built-in choice). STEN_ERR_ARG for other values. */
+sten_status sten_tune_hilo_rows(int32_t rows);
+
+/* ------------------------------------------------------------------------ */
 /* Library introspection (host only; no GPU needed)                          */
 /* ------------------------------------------------------------------------ */
 

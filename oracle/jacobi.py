@@ -47,6 +47,8 @@ __all__ = [
     "hilo_decode",
     "bound_hilo",
     "HILO_QBITS",
+    "hilo_sweep_model",
+    "jacobi5_hilo_model",
     "error_report",
 ]
 
@@ -244,15 +246,113 @@ def bound_hilo(u0, T: int, c=0.25) -> np.ndarray:
     """Componentwise bound on |y - y64| for the hi/lo form after T sweeps.
 
     Encoding the input and re-quantising after each sweep each perturb a value
-    v by at most half a quantum, delta/2 <= 2^-40 |hi| <= 2^-40 (1 + 2^-22) |v|. The
-    compensated FP32 arithmetic of a sweep (double-word sums and the product
-    with c) adds at most 2^-44 times the sum of magnitudes it combines. These
-    perturbations pass through later sweeps with the weights of |S|, so
-    |err| <= ((T + 1) 2^-40 + T 2^-44) (1 + 2^-39)^T (|J| |u0|), plus an
-    absolute term for values whose quantum is floored at 2^-149.
+    v by at most half a quantum, delta/2 <= 2^-40 |hi| <= 2^-40 (1 + 2^-22) |v|.
+    The FP32 arithmetic of one sweep is exact up to the recursive sums of the
+    low parts: four lo terms (each <= 2^-24 |h|) and three TwoSum errors (each
+    <= 2^-24 times a partial sum), so at most about 17 * 2^-48 times the sum
+    of the neighbour magnitudes; a general c adds a double-word product
+    (20 * 2^-48 in all). These perturbations pass through later sweeps with the
+    weights of |S|, so
+    |err| <= ((T + 1) 2^-40 (1 + 2^-22) + T a) (1 + 2^-39)^T (|J| |u0|), a as above,
+    plus an absolute term for values whose quantum is floored at 2^-149.
     """
-    per = (T + 1) * 2.0 ** -40 * (1.0 + 2.0 ** -22) + T * 2.0 ** -44
-    return per * (1.0 + 2.0 ** -39) ** T * abs_reference(u0, T, c) + (T + 1) * 2.0 ** -150
+    cf = float(c)
+    m, _ = np.frexp(abs(cf))
+    a = 17 * 2.0 ** -48 if (cf != 0.0 and m == 0.5) else 20 * 2.0 ** -48
+    per = (T + 1) * 2.0 ** -40 * (1.0 + 2.0 ** -22) + T * a
+    return per * (1.0 + 2.0 ** -39) ** T * abs_reference(u0, T, c) + (T + 1) * 2.0 ** -149
+
+
+# ---------------------------------------------------------------------------
+# Bit-level model of the hi/lo sweep (its steps in order, NumPy float32)
+# ---------------------------------------------------------------------------
+
+def _delta_exp32(h: np.ndarray) -> np.ndarray:
+    """k with delta(h) = 2^k, from the FP32 exponent field of h (see hilo_delta)."""
+    E = ((np.asarray(h, dtype=np.float32).view(np.uint32) >> 23) & 0xFF).astype(np.int32)
+    return np.maximum(np.maximum(E, 1) - 127 - 23 - HILO_QBITS, -149).astype(np.int32)
+
+
+def _two_sum(a: np.ndarray, b: np.ndarray):
+    """Knuth's TwoSum in FP32: s = fl(a + b) and e with s + e == a + b exactly."""
+    s = a + b
+    bb = s - a
+    e = (a - (s - bb)) + (b - bb)
+    return s, e
+
+
+def _hilo_requantise(H: np.ndarray, L: np.ndarray):
+    """(H, L) with |L| <= ulp(H)/2 -> (hi, q); q = +32768 moves one ulp into hi."""
+    k = _delta_exp32(H)
+    qf = np.rint(np.ldexp(L, -k)).astype(np.float32)
+    over = qf > 32767
+    if np.any(over):
+        H = H.copy()
+        L = L.copy()
+        ulp = np.ldexp(np.float32(1.0), k[over] + 16).astype(np.float32)
+        H[over] = H[over] + ulp
+        L[over] = L[over] - ulp
+        k2 = _delta_exp32(H[over])
+        qf[over] = np.rint(np.ldexp(L[over], -k2)).astype(np.float32)
+    return H, qf.astype(np.int16)
+
+
+def hilo_sweep_model(hi: np.ndarray, q: np.ndarray, c=0.25):
+    """One sweep of the hi/lo form on an encoded grid, step by step in FP32.
+
+    decode each point to (h, l = q * delta(h)); for each interior point,
+    s1,e1 = TwoSum(N.h, S.h); s2,e2 = TwoSum(s1, W.h); s3,e3 = TwoSum(s2, E.h);
+    low = (((N.l + S.l) + W.l) + E.l) + ((e1 + e2) + e3); (H, L) = TwoSum(s3, low);
+    scale by c (exact for a power of two, else a double-word product using the
+    exact FP32 product error); re-encode. The ring is unchanged.
+    """
+    hi = np.asarray(hi, dtype=np.float32)
+    q = np.asarray(q, dtype=np.int16)
+    out_h = hi.copy()
+    out_q = q.copy()
+    if hi.shape[0] < 3 or hi.shape[1] < 3:
+        return out_h, out_q
+    lo = np.ldexp(q.astype(np.float32), _delta_exp32(hi)).astype(np.float32)
+    nh, sh, wh, eh = hi[:-2, 1:-1], hi[2:, 1:-1], hi[1:-1, :-2], hi[1:-1, 2:]
+    nl, sl, wl, el = lo[:-2, 1:-1], lo[2:, 1:-1], lo[1:-1, :-2], lo[1:-1, 2:]
+    s1, e1 = _two_sum(nh, sh)
+    s2, e2 = _two_sum(s1, wh)
+    s3, e3 = _two_sum(s2, eh)
+    low = (((nl + sl) + wl) + el) + ((e1 + e2) + e3)
+    H, L = _two_sum(s3, low)
+    cf = float(c)
+    c_hi = np.float32(cf)
+    c_lo = np.float32(cf - float(c_hi))
+    m, _ = np.frexp(abs(cf))
+    if cf != 0.0 and m == 0.5 and c_lo == 0:
+        H = H * c_hi
+        L = L * c_hi
+    else:
+        p = H * c_hi
+        # exact error of the FP32 product: H*c_hi has 48 bits, exact in FP64
+        ep = (H.astype(np.float64) * np.float64(c_hi) - p.astype(np.float64)).astype(np.float32)
+        ep = ep + (H * c_lo + L * c_hi)
+        H = p + ep
+        L = ep - (H - p)
+    Hn, qn = _hilo_requantise(H.astype(np.float32), L.astype(np.float32))
+    out_h[1:-1, 1:-1] = Hn
+    out_q[1:-1, 1:-1] = qn
+    return out_h, out_q
+
+
+def jacobi5_hilo_model(u0, T: int, c=0.25) -> np.ndarray:
+    """FP64 result of the hi/lo form: encode u0, T model sweeps, decode; ring copied from u0."""
+    u0 = np.asarray(u0, dtype=np.float64)
+    hi, q = hilo_encode(u0)
+    for _ in range(T):
+        hi, q = hilo_sweep_model(hi, q, c)
+    out = hilo_decode(hi, q)
+    if u0.shape[0] >= 1 and u0.shape[1] >= 1:
+        out[0, :] = u0[0, :]
+        out[-1, :] = u0[-1, :]
+        out[:, 0] = u0[:, 0]
+        out[:, -1] = u0[:, -1]
+    return out
 
 
 def error_report(y, y_ref, absref) -> dict:

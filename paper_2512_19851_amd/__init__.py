@@ -9,6 +9,17 @@ library is missing.
 """
 
 from ._lib import StenError, load  # noqa: F401
-from .ops import jacobi5, set_sweep_rows, sweep  # noqa: F401
+from .ops import (  # noqa: F401
+    HiLoGrid,
+    hilo_decode,
+    hilo_encode,
+    jacobi5,
+    jacobi5_hilo,
+    jacobi5_hilo_encoded,
+    set_hilo_rows,
+    set_sweep_rows,
+    sweep,
+)
 
-__all__ = ["StenError", "load", "jacobi5", "set_sweep_rows", "sweep"]
+__all__ = ["StenError", "load", "jacobi5", "jacobi5_hilo", "jacobi5_hilo_encoded", "hilo_encode",
+           "hilo_decode", "HiLoGrid", "set_sweep_rows", "set_hilo_rows", "sweep"]

@@ -59,6 +59,13 @@ SIGNATURES = {
     "sten_tune_sweep_rows": (ctypes.c_int, [_i32]),
     "sten_sweep_f64": (ctypes.c_int, [_vp, _vp, _i64, _i64, _i64, _f64, _vp]),
     "sten_sweep_f32": (ctypes.c_int, [_vp, _vp, _i64, _i64, _i64, _f32, _vp]),
+    "sten_hilo_bytes": (_sz, [_i64, _i64]),
+    "sten_jacobi5_f64_hilo_work_bytes": (_sz, [_i64, _i64]),
+    "sten_hilo_encode": (ctypes.c_int, [_vp, _vp, _i64, _i64, _i64, _vp]),
+    "sten_hilo_decode": (ctypes.c_int, [_vp, _vp, _i64, _i64, _i64, _vp]),
+    "sten_jacobi5_hilo": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, _i64, _i32, _f64, _vp]),
+    "sten_jacobi5_f64_hilo": (ctypes.c_int, [_vp, _vp, _vp, _sz, _i64, _i64, _i64, _i32, _f64, _vp]),
+    "sten_tune_hilo_rows": (ctypes.c_int, [_i32]),
 }
 
 _lib = None

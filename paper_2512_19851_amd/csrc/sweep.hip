@@ -207,9 +207,9 @@ void launch_sweep_rows(const T* in, T* out, int H, int W, int64_t ld, T c, hipSt
 template <typename T, int V>
 void launch_sweep(const T* in, T* out, int H, int W, int64_t ld, T c, int rows, hipStream_t s) {
     switch (rows) {
-        case 4: launch_sweep_rows<T, V, 4>(in, out, H, W, ld, c, s); break;
         case 16: launch_sweep_rows<T, V, 16>(in, out, H, W, ld, c, s); break;
-        default: launch_sweep_rows<T, V, 8>(in, out, H, W, ld, c, s); break;
+        case 8: launch_sweep_rows<T, V, 8>(in, out, H, W, ld, c, s); break;
+        default: launch_sweep_rows<T, V, 4>(in, out, H, W, ld, c, s); break;
     }
 }
 
@@ -235,7 +235,7 @@ sten_status run_jacobi5(const T* u0, T* out, T* work, int64_t H, int64_t W, int6
     constexpr int VV = 16 / (int)sizeof(T);
     const uintptr_t align_bits = (uintptr_t)u0 | (uintptr_t)out | (need_work ? (uintptr_t)work : 0);
     const bool vec_ok = (align_bits % 16 == 0) && (ld % VV == 0);
-    const int rows = g_rows_override > 0 ? g_rows_override : (sizeof(T) == 8 ? 8 : 8);
+    const int rows = g_rows_override > 0 ? g_rows_override : 4;
     const T* src = u0;
     for (int32_t k = 1; k <= T_; ++k) {
         T* dst = ((T_ - k) % 2 == 0) ? out : work;
@@ -254,7 +254,7 @@ sten_status run_sweep_once(const T* src, T* dst, int64_t H, int64_t W, int64_t l
     if (st != STEN_OK || H < 3 || W < 3) return st;
     constexpr int VV = 16 / (int)sizeof(T);
     const bool vec_ok = (((uintptr_t)src | (uintptr_t)dst) % 16 == 0) && (ld % VV == 0);
-    const int rows = g_rows_override > 0 ? g_rows_override : 8;
+    const int rows = g_rows_override > 0 ? g_rows_override : 4;
     if (vec_ok)
         launch_sweep<T, VV>(src, dst, (int)H, (int)W, ld, c, rows, stream);
     else

@@ -84,3 +84,92 @@ def sweep(src: torch.Tensor, dst: torch.Tensor, c: float = 0.25, stream=None) ->
 def set_sweep_rows(rows: int) -> None:
     """Tuning hook: rows per tile of the sweep kernels (4, 8, 16; 0 = built-in)."""
     _lib.call("sten_tune_sweep_rows", int(rows))
+
+
+# ---------------------------------------------------------------------------
+# hi/lo reduced-precision form
+# ---------------------------------------------------------------------------
+
+class HiLoGrid:
+    """An encoded grid in a device byte buffer: FP32 hi plane + int16 q plane."""
+
+    def __init__(self, buf: torch.Tensor, H: int, W: int, ld: int):
+        self.buf, self.H, self.W, self.ld = buf, H, W, ld
+
+    @property
+    def q_offset(self) -> int:
+        return (self.H * self.ld * 4 + 255) // 256 * 256
+
+    def hi(self) -> torch.Tensor:
+        n = self.H * self.ld
+        return self.buf[: n * 4].view(torch.float32).view(self.H, self.ld)[:, : self.W]
+
+    def q(self) -> torch.Tensor:
+        n = self.H * self.ld
+        o = self.q_offset
+        return self.buf[o: o + n * 2].view(torch.int16).view(self.H, self.ld)[:, : self.W]
+
+
+def hilo_empty(H: int, W: int, ld: int | None = None, device=None) -> HiLoGrid:
+    ld = W if ld is None else ld
+    nbytes = int(_lib.load().sten_hilo_bytes(H, ld))
+    buf = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device or torch.device("cuda"))
+    return HiLoGrid(buf, H, W, ld)
+
+
+def hilo_encode(x: torch.Tensor, stream=None) -> HiLoGrid:
+    """FP64 grid -> encoded grid (hi = RN32(x), q = rint((x - hi) / delta(hi)))."""
+    _check_grid(x, torch.float64, "x")
+    H, W = x.shape
+    g = hilo_empty(H, W, _ld(x), x.device)
+    _lib.call("sten_hilo_encode", x.data_ptr(), g.buf.data_ptr(), H, W, g.ld, _stream_ptr(stream))
+    return g
+
+
+def hilo_decode(g: HiLoGrid, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Encoded grid -> FP64 (exact)."""
+    if out is None:
+        out = torch.empty_strided((g.H, g.W), (g.ld, 1), dtype=torch.float64, device=g.buf.device)
+    _check_grid(out, torch.float64, "out")
+    _lib.call("sten_hilo_decode", g.buf.data_ptr(), out.data_ptr(), g.H, g.W, g.ld, _stream_ptr(stream))
+    return out
+
+
+def jacobi5_hilo_encoded(src: HiLoGrid, T: int, c: float = 0.25, dst: HiLoGrid | None = None,
+                         work: HiLoGrid | None = None, stream=None) -> HiLoGrid:
+    """T sweeps on encoded grids (state stays encoded between calls)."""
+    dev = src.buf.device
+    if dst is None:
+        dst = hilo_empty(src.H, src.W, src.ld, dev)
+    if work is None and T >= 2:
+        work = hilo_empty(src.H, src.W, src.ld, dev)
+    _lib.call("sten_jacobi5_hilo", src.buf.data_ptr(), dst.buf.data_ptr(),
+              work.buf.data_ptr() if work is not None else None,
+              src.H, src.W, src.ld, int(T), float(c), _stream_ptr(stream))
+    return dst
+
+
+def jacobi5_hilo(u0: torch.Tensor, T: int, c: float = 0.25, out: torch.Tensor | None = None,
+                 work: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """FP64 in/out through the hi/lo form: encode, T encoded sweeps, decode (ring exact)."""
+    _check_grid(u0, torch.float64, "u0")
+    H, W = u0.shape
+    ld = _ld(u0)
+    if out is None:
+        out = torch.empty_strided(u0.shape, u0.stride(), dtype=torch.float64, device=u0.device)
+    _check_grid(out, torch.float64, "out")
+    need = int(_lib.load().sten_jacobi5_f64_hilo_work_bytes(H, ld))
+    if work is None:
+        work = torch.empty(max(need, 1), dtype=torch.uint8, device=u0.device)
+    _lib.call("sten_jacobi5_f64_hilo", u0.data_ptr(), out.data_ptr(), work.data_ptr(), work.numel(),
+              H, W, ld, int(T), float(c), _stream_ptr(stream))
+    return out
+
+
+def hilo_work_bytes(H: int, W: int, ld: int | None = None) -> int:
+    return int(_lib.load().sten_jacobi5_f64_hilo_work_bytes(H, W if ld is None else ld))
+
+
+def set_hilo_rows(rows: int) -> None:
+    """Tuning hook: rows per tile of the hi/lo sweep kernel (4, 8; 0 = built-in)."""
+    _lib.call("sten_tune_hilo_rows", int(rows))

@@ -86,3 +86,77 @@ def test_encode_renormalises_top_of_range():
 def test_encode_rejects_out_of_range():
     with pytest.raises(ValueError):
         oracle.hilo_encode(np.array([1e300]))
+
+
+# ---------------------------------------------------------------------------
+# The bit-level model of the hi/lo sweep
+# ---------------------------------------------------------------------------
+
+def test_two_sum_is_error_free():
+    """s + e == a + b exactly (rational check) for FP32 inputs of mixed magnitude."""
+    from fractions import Fraction
+
+    from oracle.jacobi import _two_sum
+
+    rng = np.random.default_rng(21)
+    a = (rng.standard_normal(300) * 10.0 ** rng.uniform(-8, 8, 300)).astype(np.float32)
+    b = (rng.standard_normal(300) * 10.0 ** rng.uniform(-8, 8, 300)).astype(np.float32)
+    s, e = _two_sum(a, b)
+    assert s.dtype == np.float32 and e.dtype == np.float32
+    for k in range(300):
+        assert Fraction(float(s[k])) + Fraction(float(e[k])) == Fraction(float(a[k])) + Fraction(float(b[k]))
+        assert s[k] == np.float32(float(a[k]) + float(b[k]))  # s is the rounded sum
+
+
+def test_model_reproduces_worked_examples_exactly():
+    """Dyadic grids with few bits are exact in hi/lo, so the model gives the hand-derived values."""
+    from tests.pins import read_golden
+
+    for name in ("worked_example_5x5.txt", "worked_example_3x4.txt"):
+        c, grids = read_golden(name)
+        for T in range(len(grids)):
+            assert np.array_equal(oracle.jacobi5_hilo_model(grids[0], T, c), grids[T])
+
+
+def test_model_keeps_harmonic_fixed_points():
+    H, W = 9, 13
+    i = np.arange(H, dtype=np.float64)[:, None]
+    j = np.arange(W, dtype=np.float64)[None, :]
+    u = 1 + 2 * i + 3 * j - i * j + (i * i - j * j)
+    assert np.array_equal(oracle.jacobi5_hilo_model(u, 5), u)
+
+
+@pytest.mark.parametrize("T,c", [(1, 0.25), (3, 0.25), (25, 0.25), (4, 0.3), (2, -0.5)])
+def test_model_within_bound_of_fp64(T, c):
+    from workloads import mixed_f64
+
+    u0 = mixed_f64(seed=T, n=96)
+    y = oracle.jacobi5_hilo_model(u0, T, c)
+    ref = oracle.jacobi5(u0, T, c)
+    assert np.all(np.abs(y - ref) <= oracle.bound_hilo(u0, T, c))
+    assert np.array_equal(y[0, :], u0[0, :]) and np.array_equal(y[:, -1], u0[:, -1])
+    assert np.max(np.abs(y - ref)) > 0  # not vacuous: the form is not FP64
+
+
+def test_model_much_better_than_fp32():
+    from workloads import mixed_f64
+
+    u0 = mixed_f64(seed=4, n=64)
+    T = 20
+    ref = oracle.jacobi5(u0, T)
+    e_hilo = np.max(np.abs(oracle.jacobi5_hilo_model(u0, T) - ref))
+    e_f32 = np.max(np.abs(oracle.jacobi5(u0.astype(np.float32), T, dtype=np.float32).astype(np.float64) - ref))
+    assert e_hilo * 1e4 < e_f32
+
+
+def test_requantise_renormalises():
+    from oracle.jacobi import _hilo_requantise
+
+    # L = +ulp(1)/2 = 2^-24 with H = 1: q would be 32768 -> hi = 1 + 2^-23, q = -32768
+    H = np.array([1.0, -3.0], dtype=np.float32)
+    L = np.array([2.0 ** -24, 2.0 ** -23], dtype=np.float32)  # -3 has ulp 2^-22; +2^-23 is half an ulp
+    hi, q = _hilo_requantise(H, L)
+    assert hi[0] == np.float32(1.0 + 2.0 ** -23) and q[0] == -32768
+    assert hi[1] == np.float32(-3.0 + 2.0 ** -22) and q[1] == -32768
+    dec = oracle.hilo_decode(hi, q)
+    assert dec[0] == 1.0 + 2.0 ** -24 and dec[1] == -3.0 + 2.0 ** -23
