@@ -154,9 +154,124 @@ sten_status sten_jacobi5_f64_hilo(const double* u0, double* out, void* work, siz
                                   int64_t H, int64_t W, int64_t ld, int32_t T, double c,
                                   hipStream_t stream);
 
-/* Tuning hook: output rows per workgroup tile of the hi/lo sweep kernel (4 or
- * 8; 0 restores the built-in choice). STEN_ERR_ARG for other values. */
-sten_status sten_tune_hilo_rows(int32_t rows);
+/* Tuning hook: kernel variant of the hi/lo sweep. 1: register tiles of 4
+ * rows x 4 points per lane; 2: 8 rows x 4 points; 3: 4 rows x 8 points; 4: 2
+ * rows x 8 points; 5: row streaming over 16-row strips with loads 4 rows
+ * ahead; 6: the same over 32-row strips; 0: built-in choice. All variants
+ * give the same bits. STEN_ERR_ARG for other values. */
+sten_status sten_tune_hilo_variant(int32_t variant);
+
+/* ------------------------------------------------------------------------ */
+/* Batched form: many uneven grids in one persistent launch (extension)     */
+/* ------------------------------------------------------------------------ */
+/*
+ * The paper runs one kernel per chare per iteration with many chares per GPU
+ * (over-decomposition, Section III-C). Here a whole batch of independent FP32
+ * grids, each iterated T times with the method, runs in one persistent
+ * kernel: workgroups pull grids from an atomic queue (largest first) and run
+ * all T sweeps of a grid with workgroup barriers only; grids whose ping-pong
+ * pair fits the workgroup's LDS budget never touch HBM between load and store.
+ * Results are bit-identical to sten_jacobi5_f32 on each grid.
+ */
+
+/* One grid of a batch: u0 [in], out [out], work [tmp, may be NULL when the
+ * plan keeps the grid in LDS or T < 2], each H x W FP32 with row stride ld. */
+typedef struct {
+    const float* u0;
+    float* out;
+    float* work;
+    int32_t H, W, ld, reserved;
+} sten_inst;
+
+/* Opaque host-side plan (owned by the caller; free with sten_batch_destroy). */
+typedef struct sten_batch_plan_s* sten_batch_handle;
+
+/* Device workspace bytes a plan of `count` grids needs (queue counter + descriptors). */
+size_t sten_batch_workspace_bytes(int32_t count);
+
+/*
+ * Build a plan: validate every grid (STEN_ERR_ARG/PTR/ALIAS as for the plain
+ * calls; a grid that sweeps in global memory with T >= 2 needs `work`), pick
+ * the launch configuration (block size, LDS budget per workgroup, workgroups
+ * per CU) from the tuning cache at tune_cache_path when it holds this batch's
+ * key (else built-in defaults; the path may be NULL), classify and sort the
+ * grids, and upload the sorted descriptors into dev_ws (device memory,
+ * 256-byte aligned, >= sten_batch_workspace_bytes(count), else
+ * STEN_ERR_WORKSPACE) with an async copy on `stream`. The plan keeps the
+ * pointers: the buffers must stay valid while the plan is used.
+ */
+sten_status sten_batch_plan(const sten_inst* insts, int32_t count, int32_t T, float c,
+                            const char* tune_cache_path, void* dev_ws, size_t ws_bytes,
+                            sten_batch_handle* plan, hipStream_t stream);
+
+/* Run the plan: a queue-reset kernel and the persistent kernel on `stream`.
+ * Allocates nothing and issues no memset, so it can be captured in a HIP
+ * graph. Runs of one plan must not overlap (they share the queue counter). */
+sten_status sten_batch_run(sten_batch_handle plan, hipStream_t stream);
+
+/* Autotuner: time every candidate configuration (block 256/512/1024 x LDS
+ * budget 32/64/80/160 KiB within the device limit) on this batch, `reps`
+ * runs each with HIP events (synchronises `stream`), keep the fastest in the
+ * plan, report its time per run in *best_us (may be NULL) and append it to
+ * the cache file (when the path is not NULL) for later sten_batch_plan calls.
+ * Overwrites the grids' outputs. */
+sten_status sten_batch_autotune(sten_batch_handle plan, const char* tune_cache_path, int32_t reps,
+                                float* best_us, hipStream_t stream);
+
+/* Set the launch configuration of a plan explicitly (block 64..1024, a power
+ * of two; LDS budget in bytes, clamped to the device limit; workgroups per
+ * CU 1..32) and re-classify its grids. STEN_ERR_ARG for values out of range. */
+sten_status sten_batch_configure(sten_batch_handle plan, int32_t block, int32_t lds_bytes, int32_t wg_per_cu,
+                                 hipStream_t stream);
+
+/* Plan introspection: info[0..6] = block, LDS bytes, workgroups per CU, grid
+ * size, grids kept in LDS, grids swept in global memory, grids only copied. */
+sten_status sten_batch_plan_info(sten_batch_handle plan, int32_t* info, int32_t n);
+
+/* Free the host-side plan (device workspace stays the caller's). */
+sten_status sten_batch_destroy(sten_batch_handle plan);
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint: reverse mode of the FP32 method (extension; not in the paper)   */
+/* ------------------------------------------------------------------------ */
+/*
+ * For L = sum(w * u_T), u_T the grid after T sweeps of the method from u0:
+ * dL/du0 = (S^T)^T w, where one transposed sweep is, for every point n,
+ *     (S^T g)[n] = [n on the ring] g[n] + c * (sum of g over n's interior neighbours)
+ * (neighbour terms in the order N, S, W, E, exact zeros for missing ones,
+ * FP32), and dL/dc = sum_k sum_{interior m} lambda_{k+1}[m] * nbrsum(u_k)[m]
+ * with lambda_k = dL/du_k, which needs the forward states u_0..u_{T-1}.
+ */
+
+/* Doubles of `partials` the adjoint calls need for an H x W grid. */
+size_t sten_adjoint_partials_len(int64_t H, int64_t W);
+
+/* Forward FP32 method recording every state: states holds T+1 grids, state k
+ * at states + k * H * ld (row stride ld); state 0 is a copy of u0, state k
+ * the grid after k sweeps (bit-identical to sten_jacobi5_f32 with T = k). */
+sten_status sten_jacobi5_f32_states(const float* u0, float* states, int64_t H, int64_t W, int64_t ld,
+                                    int32_t T, float c, hipStream_t stream);
+
+/* gin = dL/du0 for dL/du_T = gout: T transposed sweeps (work: second
+ * ping-pong grid, needed when T >= 2). No two of gout, gin, work may overlap. */
+sten_status sten_jacobi5_adjoint_f32(const float* gout, float* gin, float* work, int64_t H, int64_t W,
+                                     int64_t ld, int32_t T, float c, hipStream_t stream);
+
+/*
+ * nsteps transposed sweeps over one segment of recorded states, for
+ * checkpointed reverse passes: lam_in = dL/du_{k1}; states[s] = u_{k0+s}
+ * (stride H * ld, s < nsteps, k1 = k0 + nsteps; may be NULL when dL/dc is not
+ * wanted); lam_out = dL/du_{k0}. When partials (device, at least
+ * sten_adjoint_partials_len(H, W) doubles) and states are given, each step
+ * adds its dL/dc contribution into per-workgroup partial sums (FP64); reset
+ * != 0 overwrites them first. Deterministic.
+ */
+sten_status sten_jacobi5_adjoint_f32_seg(const float* lam_in, const float* states, int32_t nsteps,
+                                         float* lam_out, float* work, double* partials, int32_t reset,
+                                         int64_t H, int64_t W, int64_t ld, float c, hipStream_t stream);
+
+/* *out = sum of partials[0..n) in a fixed order (one workgroup). */
+sten_status sten_reduce_f64(const double* partials, int64_t n, double* out, hipStream_t stream);
 
 /* ------------------------------------------------------------------------ */
 /* Library introspection (host only; no GPU needed)                          */

@@ -42,6 +42,8 @@ __all__ = [
     "abs_reference",
     "gamma",
     "bound_fp32",
+    "bound_adjoint_fp32",
+    "bound_grad_c_fp32",
     "hilo_delta",
     "hilo_encode",
     "hilo_decode",
@@ -189,6 +191,62 @@ def bound_fp32(u0, T: int, c=0.25) -> np.ndarray:
     exact_c = cf != 0.0 and np.float32(cf) == cf and np.frexp(abs(cf))[0] == 0.5
     g = gamma(3, u) if exact_c else gamma(5, u)
     return T * g * (1.0 + g) ** T * abs_reference(u0, T, c)
+
+
+def bound_adjoint_fp32(w, T: int, c=0.25) -> np.ndarray:
+    """Componentwise bound on |g32 - g64| after T FP32 transposed sweeps of FP32-exact w.
+
+    One transposed sweep adds at most four neighbour terms (three additions),
+    multiplies by c (exact for a power of two) and, on the ring, adds the
+    point's own value: at most gamma_4 (gamma_5 for a general c) times the sum
+    of the magnitudes combined, i.e. of |S^T| |g|. As for the forward method,
+    |err| <= T g (1 + g)^T (|J|^T |w|), and |J|^T |w| is the adjoint applied to
+    |w| with |c| (all weights nonnegative).
+    """
+    u = 2.0 ** -24
+    cf = float(c)
+    m, _ = np.frexp(abs(cf))
+    g = gamma(4, u) if (cf != 0.0 and m == 0.5) else gamma(5, u)
+    return T * g * (1.0 + g) ** T * jacobi5_adjoint(np.abs(np.asarray(w, dtype=np.float64)), T, abs(cf))
+
+
+def bound_grad_c_fp32(u0, w, T: int, c=0.25) -> float:
+    """Bound on |dL/dc (FP32 forward states + FP32 adjoint, FP64 dot) - dL/dc (FP64)|.
+
+    Per step k the computed term is sum_m lam^_{k+1}[m] * nbrsum^_k[m] with
+    |lam^_{k+1} - lam_{k+1}| <= G_{k+1} (bound_adjoint_fp32 after T-k-1 steps)
+    and |nbrsum^_k - nbrsum(u_k)| <= E_k = nbrsum(F_k) + gamma_3 nbrsum(|u_k| + F_k),
+    F_k = bound_fp32(u0, k) the forward state error; so the step's error is at
+    most sum_m G_{k+1} (|nbrsum(u_k)| + E_k) + |lam_{k+1}| E_k. The FP64
+    products and sums add a relative 2^-40 of the sum of magnitudes.
+    """
+    u0 = np.asarray(u0, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    H, W = u0.shape
+    if H < 3 or W < 3 or T == 0:
+        return 0.0
+    g3 = gamma(3, 2.0 ** -24)
+    states = jacobi5_states(u0, T, c)
+    lams = [None] * (T + 1)
+    lams[T] = w.copy()
+    for k in range(T - 1, -1, -1):
+        lams[k] = sweep_adjoint(lams[k + 1], c)
+
+    def nsum(a):
+        return a[:-2, 1:-1] + a[2:, 1:-1] + a[1:-1, :-2] + a[1:-1, 2:]
+
+    total = 0.0
+    mag = 0.0
+    for k in range(T):
+        F = bound_fp32(u0, k, c)
+        au = np.abs(states[k])
+        E = nsum(F) + g3 * nsum(au + F)
+        G = bound_adjoint_fp32(w, T - k - 1, c)[1:-1, 1:-1]
+        lam = np.abs(lams[k + 1][1:-1, 1:-1])
+        ns = np.abs(nsum(states[k]))
+        total += float(np.sum(G * (ns + E) + lam * E))
+        mag += float(np.sum((lam + G) * (ns + E)))
+    return total + 2.0 ** -40 * mag
 
 
 # ---------------------------------------------------------------------------

@@ -10,16 +10,17 @@ library is missing.
 
 from ._lib import StenError, load  # noqa: F401
 from .ops import (  # noqa: F401
+    BatchPlan,
     HiLoGrid,
     hilo_decode,
     hilo_encode,
     jacobi5,
     jacobi5_hilo,
     jacobi5_hilo_encoded,
-    set_hilo_rows,
+    set_hilo_variant,
     set_sweep_rows,
     sweep,
 )
 
-__all__ = ["StenError", "load", "jacobi5", "jacobi5_hilo", "jacobi5_hilo_encoded", "hilo_encode",
-           "hilo_decode", "HiLoGrid", "set_sweep_rows", "set_hilo_rows", "sweep"]
+__all__ = ["StenError", "load", "BatchPlan", "jacobi5", "jacobi5_hilo", "jacobi5_hilo_encoded", "hilo_encode",
+           "hilo_decode", "HiLoGrid", "set_sweep_rows", "set_hilo_variant", "sweep"]

@@ -65,8 +65,29 @@ SIGNATURES = {
     "sten_hilo_decode": (ctypes.c_int, [_vp, _vp, _i64, _i64, _i64, _vp]),
     "sten_jacobi5_hilo": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, _i64, _i32, _f64, _vp]),
     "sten_jacobi5_f64_hilo": (ctypes.c_int, [_vp, _vp, _vp, _sz, _i64, _i64, _i64, _i32, _f64, _vp]),
-    "sten_tune_hilo_rows": (ctypes.c_int, [_i32]),
+    "sten_tune_hilo_variant": (ctypes.c_int, [_i32]),
+    "sten_batch_workspace_bytes": (_sz, [_i32]),
+    "sten_batch_plan": (ctypes.c_int, [_vp, _i32, _i32, _f32, ctypes.c_char_p, _vp, _sz,
+                                       ctypes.POINTER(_vp), _vp]),
+    "sten_batch_run": (ctypes.c_int, [_vp, _vp]),
+    "sten_batch_autotune": (ctypes.c_int, [_vp, ctypes.c_char_p, _i32, ctypes.POINTER(_f32), _vp]),
+    "sten_batch_plan_info": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), _i32]),
+    "sten_batch_configure": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp]),
+    "sten_batch_destroy": (ctypes.c_int, [_vp]),
+    "sten_adjoint_partials_len": (_sz, [_i64, _i64]),
+    "sten_jacobi5_f32_states": (ctypes.c_int, [_vp, _vp, _i64, _i64, _i64, _i32, _f32, _vp]),
+    "sten_jacobi5_adjoint_f32": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, _i64, _i32, _f32, _vp]),
+    "sten_jacobi5_adjoint_f32_seg": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _vp, _i32, _i64, _i64, _i64,
+                                                    _f32, _vp]),
+    "sten_reduce_f64": (ctypes.c_int, [_vp, _i64, _vp, _vp]),
 }
+
+
+class StenInst(ctypes.Structure):
+    """Mirror of sten_inst in include/sten.h."""
+
+    _fields_ = [("u0", _vp), ("out", _vp), ("work", _vp), ("H", _i32), ("W", _i32), ("ld", _i32),
+                ("reserved", _i32)]
 
 _lib = None
 

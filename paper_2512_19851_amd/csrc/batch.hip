@@ -1,0 +1,509 @@
+// Batched form of the five-point Jacobi method: many independent grids of
+// uneven size, each iterated T times, in ONE persistent kernel launch.
+//
+// The paper runs one generated kernel per chare per iteration, with many
+// chares per GPU (over-decomposition, Section III-C). For small grids that
+// model is launch-bound: 1024 grids x T sweeps would be 1024*T launches. Here
+// every workgroup instead pulls whole grids from an atomic work queue and runs
+// all T sweeps of a grid itself, separated only by workgroup barriers:
+//  * grids whose two ping-pong buffers fit the workgroup's LDS budget are
+//    loaded once, swept T times entirely in LDS and written back once;
+//  * larger grids sweep between the caller's out/work buffers in global
+//    memory; their working set stays in L2 / Infinity Cache across sweeps.
+// The host plan sorts grids by estimated cost (largest first) so the dynamic
+// queue performs longest-processing-time list scheduling, and uploads the
+// sorted descriptors to caller-provided device workspace. A run is two kernel
+// launches (queue reset + persistent sweep kernel) and no allocation or
+// memset, so it can be captured in a HIP graph.
+//
+// The arithmetic per point is the listing's (Section III-A) in FP32,
+// c * (((N + S) + W) + E), bit-identical to the single-grid FP32 path.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace sten {
+namespace {
+
+enum : int32_t { MODE_COPY = 0, MODE_LDS = 1, MODE_GLOBAL = 2 };
+
+struct alignas(16) Desc {
+    const float* u0;
+    float* out;
+    float* work;
+    int32_t H, W, ld, mode;
+};
+
+constexpr size_t kCounterBytes = 256;
+
+// Interior point p (0-based, row-major over the (H-2) x (W-2) interior) of a
+// grid with interior width w: advance by `step` points at a time without
+// dividing in the loop.
+struct Walker {
+    int i, j;       // current point (grid coordinates, 1-based interior)
+    int di, dj;     // step as whole rows + remaining columns
+    int w;          // interior width
+    __device__ void init(int p, int step, int width) {
+        w = width;
+        i = 1 + p / w;
+        j = 1 + p % w;
+        di = step / w;
+        dj = step % w;
+    }
+    __device__ void next() {
+        i += di;
+        j += dj;
+        if (j > w) {
+            j -= w;
+            i += 1;
+        }
+    }
+};
+
+__device__ __forceinline__ float stencil(float n, float s, float w, float e, float c) {
+    float t = n + s;
+    t = t + w;
+    t = t + e;
+    return c * t;
+}
+
+__device__ void run_copy(const Desc& d) {
+    const int n = d.H * d.W;
+    for (int p = threadIdx.x; p < n; p += blockDim.x) {
+        const int i = p / d.W;
+        const int j = p - i * d.W;
+        d.out[(int64_t)i * d.ld + j] = d.u0[(int64_t)i * d.ld + j];
+    }
+}
+
+// T sweeps with both buffers in LDS (packed rows, stride W).
+__device__ void run_lds(const Desc& d, int T, float c, float* lds) {
+    const int H = d.H, W = d.W;
+    const int n = H * W;
+    float* A = lds;
+    float* B = lds + n;
+    for (int p = threadIdx.x; p < n; p += blockDim.x) {
+        const int i = p / W;
+        const int j = p - i * W;
+        const float v = d.u0[(int64_t)i * d.ld + j];
+        A[p] = v;
+        B[p] = v;
+    }
+    __syncthreads();
+    const int w = W - 2;
+    const int m = (H - 2) * w;
+    for (int t = 0; t < T; ++t) {
+        Walker it;
+        it.init(threadIdx.x, blockDim.x, w);
+        for (int p = threadIdx.x; p < m; p += blockDim.x) {
+            const int q = it.i * W + it.j;
+            B[q] = stencil(A[q - W], A[q + W], A[q - 1], A[q + 1], c);
+            it.next();
+        }
+        __syncthreads();
+        float* tmp = A;
+        A = B;
+        B = tmp;
+    }
+    for (int p = threadIdx.x; p < n; p += blockDim.x) {
+        const int i = p / W;
+        const int j = p - i * W;
+        d.out[(int64_t)i * d.ld + j] = A[p];
+    }
+}
+
+// T sweeps between the grid's out and work buffers in global memory.
+__device__ void run_global(const Desc& d, int T, float c) {
+    const int H = d.H, W = d.W;
+    const int64_t ld = d.ld;
+    // ring of u0 into out (and work when it is written)
+    const int nring = 2 * W + 2 * (H - 2);
+    for (int r = threadIdx.x; r < nring; r += blockDim.x) {
+        int i, j;
+        if (r < W) {
+            i = 0;
+            j = r;
+        } else if (r < 2 * W) {
+            i = H - 1;
+            j = r - W;
+        } else {
+            const int k = r - 2 * W;
+            i = 1 + (k >> 1);
+            j = (k & 1) ? W - 1 : 0;
+        }
+        const float v = d.u0[i * ld + j];
+        d.out[i * ld + j] = v;
+        if (T >= 2) d.work[i * ld + j] = v;
+    }
+    const int w = W - 2;
+    const int m = (H - 2) * w;
+    const float* src = d.u0;
+    for (int k = 1; k <= T; ++k) {
+        float* dst = ((T - k) % 2 == 0) ? d.out : d.work;
+        Walker it;
+        it.init(threadIdx.x, blockDim.x, w);
+        for (int p = threadIdx.x; p < m; p += blockDim.x) {
+            const int64_t q = (int64_t)it.i * ld + it.j;
+            dst[q] = stencil(src[q - ld], src[q + ld], src[q - 1], src[q + 1], c);
+            it.next();
+        }
+        __syncthreads();  // this sweep's writes are visible to the whole workgroup before the next reads
+        src = dst;
+    }
+}
+
+__global__ void batch_reset_kernel(uint32_t* counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
+}
+
+__global__ void batch_kernel(const Desc* __restrict__ descs, uint32_t* __restrict__ counter, int count, int T,
+                             float c) {
+    extern __shared__ float lds[];
+    __shared__ int s_idx;
+    for (;;) {
+        if (threadIdx.x == 0) s_idx = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int idx = s_idx;
+        __syncthreads();
+        if (idx >= count) break;  // every workgroup reaches this once the queue is drained
+        const Desc d = descs[idx];
+        if (d.mode == MODE_LDS)
+            run_lds(d, T, c, lds);
+        else if (d.mode == MODE_GLOBAL)
+            run_global(d, T, c);
+        else
+            run_copy(d);
+        __syncthreads();
+    }
+}
+
+struct Config {
+    int block = 512;
+    int lds_bytes = 160 * 1024;  // clamped to the device limit at plan time
+    int wg_per_cu = 1;
+};
+
+}  // namespace
+}  // namespace sten
+
+struct sten_batch_plan_s {
+    int count = 0;
+    int T = 0;
+    float c = 0.25f;
+    sten::Config cfg;
+    int grid = 0;
+    int n_lds = 0, n_global = 0, n_copy = 0;
+    sten::Desc* d_descs = nullptr;
+    uint32_t* d_counter = nullptr;
+    std::vector<sten::Desc> h_descs;
+    std::vector<sten_inst> h_insts;  // caller order, kept for re-planning
+};
+
+namespace sten {
+namespace {
+
+std::mutex g_cache_mutex;
+
+// Cache key: T and a coarse histogram of grid sizes (enough to separate workloads).
+std::string batch_key(const sten_inst* insts, int count, int T) {
+    uint64_t h = 1469598103934665603ull;
+    int64_t total = 0;
+    for (int k = 0; k < count; ++k) {
+        const uint64_t v = ((uint64_t)(uint32_t)insts[k].H << 32) | (uint32_t)insts[k].W;
+        h = (h ^ v) * 1099511628211ull;
+        total += (int64_t)insts[k].H * insts[k].W;
+    }
+    std::ostringstream os;
+    os << "count=" << count << ";T=" << T << ";points=" << total << ";shape_hash=" << std::hex << h;
+    return os.str();
+}
+
+bool cache_lookup(const char* path, const std::string& key, Config& cfg) {
+    if (path == nullptr) return false;
+    std::lock_guard<std::mutex> lock(g_cache_mutex);
+    std::ifstream f(path);
+    if (!f) return false;
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {  // later lines win
+        const size_t sp = line.find(' ');
+        if (sp == std::string::npos || line.substr(0, sp) != key) continue;
+        Config c2;
+        if (sscanf(line.c_str() + sp + 1, "block=%d lds_bytes=%d wg_per_cu=%d", &c2.block, &c2.lds_bytes,
+                   &c2.wg_per_cu) == 3) {
+            cfg = c2;
+            found = true;
+        }
+    }
+    return found;
+}
+
+bool cache_store(const char* path, const std::string& key, const Config& cfg, float us) {
+    if (path == nullptr) return false;
+    std::lock_guard<std::mutex> lock(g_cache_mutex);
+    std::ofstream f(path, std::ios::app);
+    if (!f) return false;
+    f << key << " block=" << cfg.block << " lds_bytes=" << cfg.lds_bytes << " wg_per_cu=" << cfg.wg_per_cu
+      << " us=" << us << "\n";
+    return (bool)f;
+}
+
+int device_lds_limit() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 64 * 1024;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 64 * 1024;
+    return v;
+}
+
+int device_cus() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 256;
+    return v;
+}
+
+// Static LDS used by the kernel itself (the queue index), kept out of the budget.
+constexpr int kStaticLds = 64;
+
+sten_status validate_insts(const sten_inst* insts, int count) {
+    for (int k = 0; k < count; ++k) {
+        const sten_inst& s = insts[k];
+        if (s.H < 0 || s.W < 0) return STEN_ERR_ARG;
+        if (s.H > 0 && s.ld < s.W) return STEN_ERR_ARG;
+        if ((int64_t)s.H * s.ld > INT32_MAX) return STEN_ERR_ARG;
+        if (s.H == 0 || s.W == 0) continue;
+        if (s.u0 == nullptr || s.out == nullptr) return STEN_ERR_PTR;
+        const size_t nb = span_bytes(s.H, s.W, s.ld, sizeof(float));
+        if (overlaps(s.u0, nb, s.out, nb)) return STEN_ERR_ALIAS;
+        if (s.work != nullptr && (overlaps(s.u0, nb, s.work, nb) || overlaps(s.out, nb, s.work, nb)))
+            return STEN_ERR_ALIAS;
+    }
+    return STEN_OK;
+}
+
+// Classify, cost and sort; fills plan->h_descs and the class counts.
+void build_descs(sten_batch_plan_s* p) {
+    const int lds_floats = (p->cfg.lds_bytes - kStaticLds) / (int)sizeof(float);
+    struct Item {
+        Desc d;
+        double cost;
+    };
+    std::vector<Item> items;
+    items.reserve(p->count);
+    p->n_lds = p->n_global = p->n_copy = 0;
+    for (const sten_inst& s : p->h_insts) {
+        if (s.H == 0 || s.W == 0) continue;
+        Desc d{s.u0, s.out, s.work, s.H, s.W, s.ld, MODE_COPY};
+        double cost = (double)s.H * s.W;
+        if (s.H >= 3 && s.W >= 3 && p->T > 0) {
+            const double pts = (double)(s.H - 2) * (s.W - 2) * p->T;
+            if (2 * s.H * s.W <= lds_floats) {
+                d.mode = MODE_LDS;
+                cost = pts + 2.0 * s.H * s.W;
+            } else {
+                d.mode = MODE_GLOBAL;
+                cost = 2.5 * pts;  // global sweeps move about 2.5x the bytes of LDS sweeps per point
+            }
+        }
+        if (d.mode == MODE_LDS) ++p->n_lds;
+        else if (d.mode == MODE_GLOBAL) ++p->n_global;
+        else ++p->n_copy;
+        items.push_back({d, cost});
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
+    p->h_descs.clear();
+    for (const Item& it : items) p->h_descs.push_back(it.d);
+}
+
+sten_status finalize_plan(sten_batch_plan_s* p, hipStream_t stream) {
+    const int limit = device_lds_limit();
+    p->cfg.lds_bytes = std::min(p->cfg.lds_bytes, limit);
+    p->cfg.lds_bytes = std::max(p->cfg.lds_bytes, kStaticLds + 16);
+    build_descs(p);
+    p->grid = std::max(1, device_cus() * std::max(1, p->cfg.wg_per_cu));
+    const size_t dyn = (size_t)(p->cfg.lds_bytes - kStaticLds);
+    hipError_t e = hipFuncSetAttribute((const void*)batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)dyn);
+    if (e != hipSuccess) return hip_fail(e);
+    if (!p->h_descs.empty()) {
+        e = hipMemcpyAsync(p->d_descs, p->h_descs.data(), p->h_descs.size() * sizeof(Desc), hipMemcpyHostToDevice,
+                           stream);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    return STEN_OK;
+}
+
+sten_status launch_plan(const sten_batch_plan_s* p, hipStream_t stream) {
+    const int n = (int)p->h_descs.size();
+    if (n == 0) return STEN_OK;
+    batch_reset_kernel<<<1, 64, 0, stream>>>(p->d_counter);
+    const size_t dyn = (size_t)(p->cfg.lds_bytes - kStaticLds);
+    batch_kernel<<<p->grid, p->cfg.block, dyn, stream>>>(p->d_descs, p->d_counter, n, p->T, p->c);
+    return check_launch();
+}
+
+}  // namespace
+}  // namespace sten
+
+extern "C" {
+
+size_t sten_batch_workspace_bytes(int32_t count) {
+    if (count < 0) return 0;
+    return sten::kCounterBytes + (size_t)count * sizeof(sten::Desc);
+}
+
+sten_status sten_batch_plan(const sten_inst* insts, int32_t count, int32_t T, float c, const char* tune_cache_path,
+                            void* dev_ws, size_t ws_bytes, sten_batch_handle* plan, hipStream_t stream) {
+    using namespace sten;
+    if (plan == nullptr) return STEN_ERR_ARG;
+    *plan = nullptr;
+    if (count < 0 || T < 0) return STEN_ERR_ARG;
+    if (count > 0 && insts == nullptr) return STEN_ERR_PTR;
+    if (dev_ws == nullptr) return STEN_ERR_PTR;
+    if ((uintptr_t)dev_ws % 256 != 0) return STEN_ERR_ARG;
+    if (ws_bytes < sten_batch_workspace_bytes(count)) return STEN_ERR_WORKSPACE;
+    sten_status st = validate_insts(insts, count);
+    if (st != STEN_OK) return st;
+    if (!is_device_ptr(dev_ws)) return STEN_ERR_PTR;
+    for (int k = 0; k < count; ++k) {
+        const sten_inst& s = insts[k];
+        if (s.H == 0 || s.W == 0) continue;
+        if (!is_device_ptr(s.u0) || !is_device_ptr(s.out)) return STEN_ERR_PTR;
+    }
+    auto* p = new sten_batch_plan_s();
+    p->count = count;
+    p->T = T;
+    p->c = c;
+    p->h_insts.assign(insts, insts + count);
+    p->d_counter = (uint32_t*)dev_ws;
+    p->d_descs = (Desc*)((char*)dev_ws + kCounterBytes);
+    Config cfg;
+    if (!cache_lookup(tune_cache_path, batch_key(insts, count, T), cfg)) cfg = Config{};
+    p->cfg = cfg;
+    // a grid that needs the second buffer in global memory must have one
+    build_descs(p);
+    for (const Desc& d : p->h_descs) {
+        if (d.mode == MODE_GLOBAL && T >= 2 && (d.work == nullptr || !is_device_ptr(d.work))) {
+            delete p;
+            return STEN_ERR_PTR;
+        }
+    }
+    st = finalize_plan(p, stream);
+    if (st != STEN_OK) {
+        delete p;
+        return st;
+    }
+    *plan = p;
+    return STEN_OK;
+}
+
+sten_status sten_batch_run(sten_batch_handle plan, hipStream_t stream) {
+    if (plan == nullptr) return STEN_ERR_ARG;
+    return sten::launch_plan(plan, stream);
+}
+
+sten_status sten_batch_destroy(sten_batch_handle plan) {
+    delete plan;
+    return STEN_OK;
+}
+
+sten_status sten_batch_plan_info(sten_batch_handle plan, int32_t* info, int32_t n) {
+    if (plan == nullptr || info == nullptr || n < 7) return STEN_ERR_ARG;
+    info[0] = plan->cfg.block;
+    info[1] = plan->cfg.lds_bytes;
+    info[2] = plan->cfg.wg_per_cu;
+    info[3] = plan->grid;
+    info[4] = plan->n_lds;
+    info[5] = plan->n_global;
+    info[6] = plan->n_copy;
+    return STEN_OK;
+}
+
+sten_status sten_batch_configure(sten_batch_handle plan, int32_t block, int32_t lds_bytes, int32_t wg_per_cu,
+                                 hipStream_t stream) {
+    using namespace sten;
+    if (plan == nullptr) return STEN_ERR_ARG;
+    if (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024) return STEN_ERR_ARG;
+    if (lds_bytes < 1024 || wg_per_cu < 1 || wg_per_cu > 32) return STEN_ERR_ARG;
+    Config c;
+    c.block = block;
+    c.lds_bytes = lds_bytes;
+    c.wg_per_cu = wg_per_cu;
+    const Config saved = plan->cfg;
+    plan->cfg = c;
+    sten_status st = finalize_plan(plan, stream);
+    if (st != STEN_OK) {
+        plan->cfg = saved;
+        (void)finalize_plan(plan, stream);
+    }
+    return st;
+}
+
+sten_status sten_batch_autotune(sten_batch_handle plan, const char* tune_cache_path, int32_t reps, float* best_us,
+                                hipStream_t stream) {
+    using namespace sten;
+    if (plan == nullptr || reps < 1) return STEN_ERR_ARG;
+    const int limit = device_lds_limit();
+    std::vector<Config> cands;
+    for (int block : {256, 512, 1024}) {
+        for (int kb : {32, 64, 80, 160}) {
+            if (kb * 1024 > limit) continue;
+            Config c;
+            c.block = block;
+            c.lds_bytes = kb * 1024;
+            c.wg_per_cu = std::max(1, std::min(limit / (kb * 1024), 2048 / block));
+            cands.push_back(c);
+        }
+    }
+    hipEvent_t e0, e1;
+    hipError_t he = hipEventCreate(&e0);
+    if (he != hipSuccess) return hip_fail(he);
+    he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(he);
+    }
+    const Config saved = plan->cfg;
+    Config best = saved;
+    float best_t = 1e30f;
+    sten_status st = STEN_OK;
+    for (const Config& cand : cands) {
+        plan->cfg = cand;
+        if ((st = finalize_plan(plan, stream)) != STEN_OK) break;
+        if ((st = launch_plan(plan, stream)) != STEN_OK) break;  // warm-up
+        if ((he = hipEventRecord(e0, stream)) != hipSuccess) { st = hip_fail(he); break; }
+        for (int r = 0; r < reps && st == STEN_OK; ++r) st = launch_plan(plan, stream);
+        if (st != STEN_OK) break;
+        if ((he = hipEventRecord(e1, stream)) != hipSuccess) { st = hip_fail(he); break; }
+        if ((he = hipEventSynchronize(e1)) != hipSuccess) { st = hip_fail(he); break; }
+        float ms = 0.0f;
+        if ((he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { st = hip_fail(he); break; }
+        const float us = ms * 1000.0f / reps;
+        if (us < best_t) {
+            best_t = us;
+            best = cand;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    plan->cfg = (st == STEN_OK) ? best : saved;
+    sten_status st2 = finalize_plan(plan, stream);
+    if (st != STEN_OK) return st;
+    if (st2 != STEN_OK) return st2;
+    if (best_us != nullptr) *best_us = best_t;
+    if (tune_cache_path != nullptr &&
+        !cache_store(tune_cache_path, batch_key(plan->h_insts.data(), plan->count, plan->T), best, best_t))
+        return STEN_ERR_ARG;
+    return STEN_OK;
+}
+
+}  // extern "C"

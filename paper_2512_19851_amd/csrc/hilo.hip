@@ -114,6 +114,11 @@ struct HVec<4> {
     typedef float hv __attribute__((ext_vector_type(4)));
     typedef short qv __attribute__((ext_vector_type(4)));
 };
+template <>
+struct HVec<8> {
+    typedef float hv __attribute__((ext_vector_type(8)));
+    typedef short qv __attribute__((ext_vector_type(8)));
+};
 
 template <int V, bool FULL>
 __device__ __forceinline__ void load_row(const float* __restrict__ hrow, const int16_t* __restrict__ qrow, int jb,
@@ -214,6 +219,91 @@ __device__ __forceinline__ void hilo_tile(const float* __restrict__ hsrc, const 
 #pragma unroll
             for (int e = 0; e < V; ++e) oq[e] = (int16_t)qf[e];
             store_row<V>(hdst + (int64_t)k * ld, qdst + (int64_t)k * ld, jb, W, oh, oq);
+        }
+    }
+}
+
+// Full tile (ROWS output rows, every lane of the wave inside the grid), the
+// hot path: loads address a uniform row base with 32-bit lane offsets (scalar
+// base + vector offset addressing), and the two neighbours that lie in other
+// waves are fetched by one load per row - lane 0 takes the left one, lane 63
+// the right one - and decoded once.
+template <int V, int ROWS, bool POW2>
+__device__ __forceinline__ void hilo_tile_full(const float* __restrict__ hsrc, const int16_t* __restrict__ qsrc,
+                                               float* __restrict__ hdst, int16_t* __restrict__ qdst, int jb,
+                                               int lane, int W, int ld, const Coef& c) {
+    typedef typename HVec<V>::hv HV;
+    typedef typename HVec<V>::qv QV;
+    HV rh[ROWS + 2];
+    QV rq[ROWS + 2];
+#pragma unroll
+    for (int k = 0; k < ROWS + 2; ++k) {
+        const int off = k * ld + jb;
+        rh[k] = *reinterpret_cast<const HV*>(hsrc + off);
+        rq[k] = *reinterpret_cast<const QV*>(qsrc + off);
+    }
+    int eidx = -1;
+    if (lane == 0 && jb > 0) eidx = jb - 1;
+    if (lane == kWave - 1 && jb + V < W) eidx = jb + V;
+    float eh[ROWS];
+    int16_t eq[ROWS];
+#pragma unroll
+    for (int k = 0; k < ROWS; ++k) {
+        eh[k] = 0.0f;
+        eq[k] = 0;
+        if (eidx >= 0) {
+            const int off = (k + 1) * ld + eidx;
+            eh[k] = hsrc[off];
+            eq[k] = qsrc[off];
+        }
+    }
+    DW d[ROWS + 2][V];
+#pragma unroll
+    for (int k = 0; k < ROWS + 2; ++k)
+#pragma unroll
+        for (int e = 0; e < V; ++e) d[k][e] = decode(rh[k][e], (int16_t)rq[k][e]);
+#pragma unroll
+    for (int k = 0; k < ROWS; ++k) {
+        const DW edge = decode(eh[k], eq[k]);
+        DW left0 = shfl_up_dw(d[k + 1][V - 1]);
+        DW rightv = shfl_down_dw(d[k + 1][0]);
+        if (lane == 0) left0 = edge;
+        if (lane == kWave - 1) rightv = edge;
+        float oh[V], ol[V], qf[V];
+        bool over = false;
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            const DW west = (e == 0) ? left0 : d[k + 1][e > 0 ? e - 1 : 0];
+            const DW east = (e == V - 1) ? rightv : d[k + 1][e < V - 1 ? e + 1 : 0];
+            stencil_point<POW2>(d[k][e], d[k + 2][e], west, east, c, oh[e], ol[e]);
+            qf[e] = quantise(oh[e], ol[e]);
+            over = over || (qf[e] > 32767.0f);
+        }
+        if (__any(over)) {
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+                if (qf[e] > 32767.0f) renormalise(oh[e], ol[e], qf[e]);
+        }
+        HV hv;
+        QV qv;
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            hv[e] = oh[e];
+            qv[e] = (short)(int)qf[e];
+        }
+        const int off = k * ld + jb;
+        if (jb >= 1 && jb + V <= W - 1) {
+            *reinterpret_cast<HV*>(hdst + off) = hv;
+            *reinterpret_cast<QV*>(qdst + off) = qv;
+        } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const int j = jb + e;
+                if (j >= 1 && j <= W - 2) {
+                    hdst[off + e] = oh[e];
+                    qdst[off + e] = (int16_t)(int)qf[e];
+                }
+            }
         }
     }
 }
@@ -353,9 +443,14 @@ __global__ __launch_bounds__(kBlock) void hilo_sweep_kernel(const float* __restr
     const int wave_end = (jb - lane * V) + kWave * V;
     const int64_t in_off = (int64_t)(i0 - 1) * ld;
     const int64_t out_off = (int64_t)i0 * ld;
-    if (n == ROWS && wave_end <= W)
-        hilo_tile<V, ROWS, true, POW2>(hin + in_off, qin + in_off, hout + out_off, qout + out_off, n, jb, lane, W, ld, c);
-    else
+    if (n == ROWS && wave_end <= W) {
+        if constexpr (V >= 4)
+            hilo_tile_full<V, ROWS, POW2>(hin + in_off, qin + in_off, hout + out_off, qout + out_off, jb, lane, W,
+                                          (int)ld, c);
+        else
+            hilo_tile<V, ROWS, true, POW2>(hin + in_off, qin + in_off, hout + out_off, qout + out_off, n, jb, lane,
+                                           W, ld, c);
+    } else
         hilo_tile<V, ROWS, false, POW2>(hin + in_off, qin + in_off, hout + out_off, qout + out_off, n, jb, lane, W, ld, c);
 }
 
@@ -450,7 +545,7 @@ Coef make_coef(double c) {
     return k;
 }
 
-int g_hilo_rows = 0;
+int g_hilo_variant = 0;
 
 template <int V, int ROWS>
 void launch_hilo_rows(const Planes& in, const Planes& out, int H, int W, int64_t ld, const Coef& c, hipStream_t s) {
@@ -476,22 +571,34 @@ void launch_hilo_stream(const Planes& in, const Planes& out, int H, int W, int64
                                                                                  c, tiles_x);
 }
 
-template <int V>
-void launch_hilo(const Planes& in, const Planes& out, int H, int W, int64_t ld, const Coef& c, int rows,
+// Kernel variants (tuning hook): 1: tiles of 4 rows x 4 points per lane;
+// 2: 8 rows x 4 points; 3: 4 rows x 8 points; 4: 2 rows x 8 points;
+// 5: row streaming over 16-row strips (loads 4 rows ahead); 6: 32-row strips.
+constexpr int kHiloDefaultVariant = 4;
+
+template <int V, int ROWS>
+bool launch_tile_if_aligned(const Planes& in, const Planes& out, int H, int W, int64_t ld, const Coef& c,
+                            hipStream_t s) {
+    if (ld % V != 0) return false;
+    launch_hilo_rows<V, ROWS>(in, out, H, W, ld, c, s);
+    return true;
+}
+
+void launch_hilo(const Planes& in, const Planes& out, int H, int W, int64_t ld, const Coef& c, int variant,
                  hipStream_t s) {
-    if constexpr (V == 4) {
-        switch (rows) {
-            case 16: launch_hilo_stream<16, 4>(in, out, H, W, ld, c, s); return;
-            case 32: launch_hilo_stream<32, 4>(in, out, H, W, ld, c, s); return;
-            case 33: launch_hilo_stream<32, 2>(in, out, H, W, ld, c, s); return;
-            case 17: launch_hilo_stream<16, 2>(in, out, H, W, ld, c, s); return;
+    // 32-bit lane offsets inside a tile need (rows + 2) * ld well below 2^31
+    if (ld <= (int64_t(1) << 26)) {
+        switch (variant) {
+            case 2: if (launch_tile_if_aligned<4, 8>(in, out, H, W, ld, c, s)) return; break;
+            case 3: if (launch_tile_if_aligned<8, 4>(in, out, H, W, ld, c, s)) return; break;
+            case 4: if (launch_tile_if_aligned<8, 2>(in, out, H, W, ld, c, s)) return; break;
+            case 5: if (ld % 4 == 0) { launch_hilo_stream<16, 4>(in, out, H, W, ld, c, s); return; } break;
+            case 6: if (ld % 4 == 0) { launch_hilo_stream<32, 4>(in, out, H, W, ld, c, s); return; } break;
             default: break;
         }
+        if (launch_tile_if_aligned<4, 4>(in, out, H, W, ld, c, s)) return;
     }
-    switch (rows) {
-        case 4: launch_hilo_rows<V, 4>(in, out, H, W, ld, c, s); break;
-        default: launch_hilo_rows<V, 8>(in, out, H, W, ld, c, s); break;
-    }
+    launch_hilo_rows<1, 4>(in, out, H, W, ld, c, s);
 }
 
 size_t hilo_bytes(int64_t H, int64_t ld) {
@@ -525,15 +632,11 @@ sten_status run_hilo_sweeps(const Planes& src, const Planes& dst, const Planes& 
     hilo_copy_kernel<<<grid_blocks(total), 256, 0, stream>>>(src.h, src.q, dst.h, dst.q,
                                                              need_work ? work.h : nullptr,
                                                              need_work ? work.q : nullptr, H, W, ld, 0);
-    const bool vec_ok = (ld % 4 == 0);
-    const int rows = g_hilo_rows > 0 ? g_hilo_rows : 4;
+    const int variant = g_hilo_variant > 0 ? g_hilo_variant : kHiloDefaultVariant;
     Planes cur = src;
     for (int32_t k = 1; k <= T; ++k) {
         const Planes& d = ((T - k) % 2 == 0) ? dst : work;
-        if (vec_ok)
-            launch_hilo<4>(cur, d, H, W, ld, c, rows, stream);
-        else
-            launch_hilo<1>(cur, d, H, W, ld, c, rows, stream);
+        launch_hilo(cur, d, H, W, ld, c, variant, stream);
         cur = d;
     }
     return check_launch();
@@ -613,14 +716,10 @@ sten_status sten_jacobi5_f64_hilo(const double* u0, double* out, void* work, siz
     Planes cur = a;
     if (T > 0 && H >= 3 && W >= 3) {
         const Coef k = make_coef(c);
-        const bool vec_ok = (ld % 4 == 0);
-        const int rows = g_hilo_rows > 0 ? g_hilo_rows : 4;
+        const int variant = g_hilo_variant > 0 ? g_hilo_variant : kHiloDefaultVariant;
         for (int32_t s = 0; s < T; ++s) {
             const Planes& d = (s % 2 == 0) ? b : a;
-            if (vec_ok)
-                launch_hilo<4>(cur, d, h, w, ld, k, rows, stream);
-            else
-                launch_hilo<1>(cur, d, h, w, ld, k, rows, stream);
+            launch_hilo(cur, d, h, w, ld, k, variant, stream);
             cur = d;
         }
     }
@@ -628,11 +727,10 @@ sten_status sten_jacobi5_f64_hilo(const double* u0, double* out, void* work, siz
     return check_launch();
 }
 
-// Tuning hook: rows per tile of the hi/lo sweep kernel (4 or 8; 0 = built-in).
-sten_status sten_tune_hilo_rows(int32_t rows) {
-    if (rows != 0 && rows != 4 && rows != 8 && rows != 16 && rows != 17 && rows != 32 && rows != 33)
-        return STEN_ERR_ARG;
-    sten::g_hilo_rows = rows;
+// Tuning hook: kernel variant of the hi/lo sweep (1..6; 0 = built-in).
+sten_status sten_tune_hilo_variant(int32_t variant) {
+    if (variant < 0 || variant > 6) return STEN_ERR_ARG;
+    sten::g_hilo_variant = variant;
     return STEN_OK;
 }
 

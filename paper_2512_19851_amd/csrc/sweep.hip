@@ -263,6 +263,17 @@ sten_status run_sweep_once(const T* src, T* dst, int64_t H, int64_t W, int64_t l
 }
 
 }  // namespace
+
+// FP32 sweep launch for other parts of the library (no argument checks).
+void launch_sweep_f32_internal(const float* in, float* out, int H, int W, int64_t ld, float c, hipStream_t s) {
+    const bool vec_ok = (((uintptr_t)in | (uintptr_t)out) % 16 == 0) && (ld % 4 == 0);
+    const int rows = g_rows_override > 0 ? g_rows_override : 4;
+    if (vec_ok)
+        launch_sweep<float, 4>(in, out, H, W, ld, c, rows, s);
+    else
+        launch_sweep<float, 1>(in, out, H, W, ld, c, rows, s);
+}
+
 }  // namespace sten
 
 extern "C" {

@@ -170,6 +170,89 @@ def hilo_work_bytes(H: int, W: int, ld: int | None = None) -> int:
     return int(_lib.load().sten_jacobi5_f64_hilo_work_bytes(H, W if ld is None else ld))
 
 
-def set_hilo_rows(rows: int) -> None:
-    """Tuning hook: rows per tile of the hi/lo sweep kernel (4, 8; 0 = built-in)."""
-    _lib.call("sten_tune_hilo_rows", int(rows))
+def set_hilo_variant(variant: int) -> None:
+    """Tuning hook: kernel variant of the hi/lo sweep (1..6, see sten.h; 0 = built-in)."""
+    _lib.call("sten_tune_hilo_variant", int(variant))
+
+
+# ---------------------------------------------------------------------------
+# Batched form: many grids, one persistent launch
+# ---------------------------------------------------------------------------
+
+class BatchPlan:
+    """A plan over a list of FP32 grids (u0 tensors) with their out/work tensors.
+
+    plan = BatchPlan(u0s, T, c, tune_cache=path)  # allocates outs, works, workspace
+    plan.run()                                      # one persistent launch (graph-capturable)
+    plan.outs                                       # results
+    """
+
+    def __init__(self, u0s, T: int, c: float = 0.25, outs=None, works=None, tune_cache: str | None = None,
+                 stream=None):
+        import ctypes
+
+        lib = _lib.load()
+        self.T, self.c = int(T), float(c)
+        self.u0s = list(u0s)
+        for k, t in enumerate(self.u0s):
+            _check_grid(t, torch.float32, f"u0s[{k}]")
+        dev = self.u0s[0].device if self.u0s else torch.device("cuda")
+        self.outs = outs if outs is not None else [torch.empty_like(t) for t in self.u0s]
+        if works is None:
+            works = [torch.empty_like(t) if (T >= 2 and t.shape[0] >= 3 and t.shape[1] >= 3) else None
+                     for t in self.u0s]
+        self.works = works
+        n = len(self.u0s)
+        arr = (_lib.StenInst * max(n, 1))()
+        for k in range(n):
+            u, o, w = self.u0s[k], self.outs[k], self.works[k]
+            arr[k].u0 = u.data_ptr()
+            arr[k].out = o.data_ptr()
+            arr[k].work = w.data_ptr() if w is not None else None
+            arr[k].H, arr[k].W = int(u.shape[0]), int(u.shape[1])
+            arr[k].ld = _ld(u)
+            arr[k].reserved = 0
+        self._arr = arr
+        nbytes = int(lib.sten_batch_workspace_bytes(n))
+        self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
+        self._handle = ctypes.c_void_p()
+        path = tune_cache.encode() if tune_cache else None
+        _lib.check("sten_batch_plan", lib.sten_batch_plan(ctypes.cast(arr, ctypes.c_void_p), n, self.T, self.c,
+                                                          path, self.ws.data_ptr(), self.ws.numel(),
+                                                          ctypes.byref(self._handle), _stream_ptr(stream)))
+
+    def run(self, stream=None) -> list:
+        _lib.call("sten_batch_run", self._handle, _stream_ptr(stream))
+        return self.outs
+
+    def autotune(self, tune_cache: str | None = None, reps: int = 3, stream=None) -> float:
+        import ctypes
+
+        best = ctypes.c_float(0.0)
+        path = tune_cache.encode() if tune_cache else None
+        _lib.call("sten_batch_autotune", self._handle, path, int(reps), ctypes.byref(best), _stream_ptr(stream))
+        return float(best.value)
+
+    def configure(self, block: int, lds_bytes: int, wg_per_cu: int = 1, stream=None) -> None:
+        """Set block size, LDS budget per workgroup and workgroups per CU explicitly."""
+        _lib.call("sten_batch_configure", self._handle, int(block), int(lds_bytes), int(wg_per_cu),
+                  _stream_ptr(stream))
+
+    def info(self) -> dict:
+        import ctypes
+
+        buf = (ctypes.c_int32 * 7)()
+        _lib.call("sten_batch_plan_info", self._handle, buf, 7)
+        keys = ["block", "lds_bytes", "wg_per_cu", "grid", "n_lds", "n_global", "n_copy"]
+        return dict(zip(keys, list(buf)))
+
+    def close(self) -> None:
+        if getattr(self, "_handle", None) is not None and self._handle.value:
+            _lib.load().sten_batch_destroy(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

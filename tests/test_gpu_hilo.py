@@ -87,15 +87,17 @@ def test_hilo_encoded_state_between_calls(ops):
     assert np.array_equal(one, oracle.hilo_decode(hi, q))
 
 
-@pytest.mark.parametrize("rows", [4, 8])
-def test_hilo_rows_variants(ops, rows):
-    u0 = mixed_f64(seed=9, n=260)
-    ops.set_hilo_rows(rows)
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6])
+def test_hilo_kernel_variants(ops, variant):
+    """Every kernel variant gives the model's bits, on full and ragged tiles."""
+    ops.set_hilo_variant(variant)
     try:
-        say(f"hilo rows={rows}")
-        assert np.array_equal(to_host(ops.jacobi5_hilo(to_dev(u0), 3)), oracle.jacobi5_hilo_model(u0, 3))
+        for shape in [(260, 260), (131, 1029), (70, 2048)]:
+            u0 = mixed_f64(seed=variant, n=max(shape))[: shape[0], : shape[1]].copy()
+            say(f"hilo variant={variant} {shape}")
+            assert np.array_equal(to_host(ops.jacobi5_hilo(to_dev(u0), 3)), oracle.jacobi5_hilo_model(u0, 3))
     finally:
-        ops.set_hilo_rows(0)
+        ops.set_hilo_variant(0)
 
 
 def test_hilo_odd_stride(ops):
