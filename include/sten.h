@@ -157,7 +157,9 @@ sten_status sten_jacobi5_f64_hilo(const double* u0, double* out, void* work, siz
 /* Tuning hook: kernel variant of the hi/lo sweep. 1: register tiles of 4
  * rows x 4 points per lane; 2: 8 rows x 4 points; 3: 4 rows x 8 points; 4: 2
  * rows x 8 points; 5: row streaming over 16-row strips with loads 4 rows
- * ahead; 6: the same over 32-row strips; 0: built-in choice. All variants
+ * ahead; 6: the same over 32-row strips; 7: 2 rows x 4 points; 8: 1 row x
+ * 8 points; 9: 1 row x 16 points; 10: 3 rows x 8 points; 0: built-in choice
+ * (4). All variants
  * give the same bits. STEN_ERR_ARG for other values. */
 sten_status sten_tune_hilo_variant(int32_t variant);
 

@@ -119,6 +119,11 @@ struct HVec<8> {
     typedef float hv __attribute__((ext_vector_type(8)));
     typedef short qv __attribute__((ext_vector_type(8)));
 };
+template <>
+struct HVec<16> {
+    typedef float hv __attribute__((ext_vector_type(16)));
+    typedef short qv __attribute__((ext_vector_type(16)));
+};
 
 template <int V, bool FULL>
 __device__ __forceinline__ void load_row(const float* __restrict__ hrow, const int16_t* __restrict__ qrow, int jb,
@@ -573,7 +578,8 @@ void launch_hilo_stream(const Planes& in, const Planes& out, int H, int W, int64
 
 // Kernel variants (tuning hook): 1: tiles of 4 rows x 4 points per lane;
 // 2: 8 rows x 4 points; 3: 4 rows x 8 points; 4: 2 rows x 8 points;
-// 5: row streaming over 16-row strips (loads 4 rows ahead); 6: 32-row strips.
+// 5: row streaming over 16-row strips (loads 4 rows ahead); 6: 32-row strips;
+// 7: 2 rows x 4 points; 8: 1 row x 8 points; 9: 1 row x 16 points; 10: 3 rows x 8 points.
 constexpr int kHiloDefaultVariant = 4;
 
 template <int V, int ROWS>
@@ -594,6 +600,10 @@ void launch_hilo(const Planes& in, const Planes& out, int H, int W, int64_t ld, 
             case 4: if (launch_tile_if_aligned<8, 2>(in, out, H, W, ld, c, s)) return; break;
             case 5: if (ld % 4 == 0) { launch_hilo_stream<16, 4>(in, out, H, W, ld, c, s); return; } break;
             case 6: if (ld % 4 == 0) { launch_hilo_stream<32, 4>(in, out, H, W, ld, c, s); return; } break;
+            case 7: if (launch_tile_if_aligned<4, 2>(in, out, H, W, ld, c, s)) return; break;
+            case 8: if (launch_tile_if_aligned<8, 1>(in, out, H, W, ld, c, s)) return; break;
+            case 9: if (launch_tile_if_aligned<16, 1>(in, out, H, W, ld, c, s)) return; break;
+            case 10: if (launch_tile_if_aligned<8, 3>(in, out, H, W, ld, c, s)) return; break;
             default: break;
         }
         if (launch_tile_if_aligned<4, 4>(in, out, H, W, ld, c, s)) return;
@@ -729,7 +739,7 @@ sten_status sten_jacobi5_f64_hilo(const double* u0, double* out, void* work, siz
 
 // Tuning hook: kernel variant of the hi/lo sweep (1..6; 0 = built-in).
 sten_status sten_tune_hilo_variant(int32_t variant) {
-    if (variant < 0 || variant > 6) return STEN_ERR_ARG;
+    if (variant < 0 || variant > 10) return STEN_ERR_ARG;
     sten::g_hilo_variant = variant;
     return STEN_OK;
 }

@@ -87,7 +87,7 @@ def test_hilo_encoded_state_between_calls(ops):
     assert np.array_equal(one, oracle.hilo_decode(hi, q))
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7, 8, 9, 10])
 def test_hilo_kernel_variants(ops, variant):
     """Every kernel variant gives the model's bits, on full and ragged tiles."""
     ops.set_hilo_variant(variant)
