@@ -44,8 +44,14 @@ def log(msg: str) -> None:
 
 
 def source_sha(path: str) -> str:
+    """Hash of the kernel's source region (between the BEGIN/END KERNEL SOURCE markers)."""
     with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+        text = f.read()
+    a = text.find(b"BEGIN KERNEL SOURCE")
+    b = text.find(b"END KERNEL SOURCE")
+    if a >= 0 and b > a:
+        text = text[a:b]
+    return hashlib.sha256(text).hexdigest()[:16]
 
 
 def load_traffic(launch_bytes: float):
@@ -231,6 +237,39 @@ def bench_batch(ops, T: int, args) -> dict:
         "bit_identical_to_plain": bool(same),
         "interior_points_in_lds_frac": round(lds_pts / interior, 4),
     }
+
+
+def bench_tiled(ops, n: int, T: int, args, plain_sec_per_step: float) -> dict:
+    """The plain FP64 step on the same grid split into tiles with ghost exchange (one GPU)."""
+    import torch
+
+    from workloads import large_f64
+
+    log("[bench] tiled execution")
+    u0 = torch.from_numpy(large_f64(0, n)).to("cuda:0")
+    comm = torch.cuda.Stream()
+    res = {}
+    for pr, pc in ((2, 2), (4, 4)):
+        t = ops.TiledGrid(n, n, pr, pc, comm_stream=comm)
+        t.scatter(u0)
+        t.run(2)
+        torch.cuda.synchronize()
+        reps = max(3, args.steps // 4)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            t.run(T)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / reps
+        st = t.stats()
+        res[f"{pr}x{pc}"] = {
+            "ms_per_step": round(sec * 1e3, 4),
+            "effective_GBps": round(16.0 * (n - 2) ** 2 * T / sec / 1e9, 1),
+            "overhead_vs_single_grid": round(sec / plain_sec_per_step, 3),
+            "sweep_launches_per_step": st["sweep_launches"] // (reps + 1) if reps else None,
+        }
+    res["workload"] = (f"{n}x{n} FP64 N(0,1) seed 0, {T} sweeps per step, tiles with depth-1 ghosts; "
+                       "pack/unpack on a second stream, per-tile sweep kernels")
+    return res
 
 
 def bench_adjoint(T: int, args) -> dict:
@@ -439,6 +478,7 @@ def main() -> int:
         rec["extensions"] = {
             "mixed_hilo": bench_mixed(ops, n, T, args, sec_per_step),
             "batched": bench_batch(ops, T, args),
+            "tiled": bench_tiled(ops, n, T, args, sec_per_step),
             "adjoint": bench_adjoint(10, args),
         }
 

@@ -276,6 +276,53 @@ sten_status sten_jacobi5_adjoint_f32_seg(const float* lam_in, const float* state
 sten_status sten_reduce_f64(const double* partials, int64_t n, double* out, hipStream_t stream);
 
 /* ------------------------------------------------------------------------ */
+/* Tiled execution on one GPU (chares with ghost exchange)                   */
+/* ------------------------------------------------------------------------ */
+/*
+ * The paper's data layout and DAG execution (Section III-C): an H x W FP64
+ * grid split into pr x pc tiles, each with its owned block, a depth-1 ghost
+ * frame (the ghost depth of the five-point stencil), two buffers and one send
+ * buffer per neighbour edge. Before a sweep reads an array, its ghosts are
+ * refreshed when its local generation epoch differs from its ghost epoch:
+ * pack and unpack kernels on the communication stream, ordered against the
+ * compute stream by a compute event and a communication event. Results are
+ * bit-identical to sten_jacobi5_f64 on the whole grid for any tiling.
+ */
+typedef struct sten_tiled_s* sten_tiled_handle;
+
+/* Device workspace bytes for a tiling (0 when the tiling is invalid:
+ * H, W, pr, pc < 1 or more tiles than rows/columns). */
+size_t sten_tiled_workspace_bytes(int64_t H, int64_t W, int32_t pr, int32_t pc);
+
+/* Create the tiling inside dev_ws (device memory, 256-byte aligned, at least
+ * sten_tiled_workspace_bytes). Tile (a, b) owns rows [a H/pr, (a+1) H/pr) and
+ * columns [b W/pc, (b+1) W/pc) (integer division). Host-side handle. */
+sten_status sten_tiled_create(int64_t H, int64_t W, int32_t pr, int32_t pc, void* dev_ws, size_t ws_bytes,
+                              sten_tiled_handle* out);
+
+/* Load a grid u (row stride ld) into both buffers of every tile; ghosts become
+ * stale (epochs advance). */
+sten_status sten_tiled_scatter(sten_tiled_handle t, const double* u, int64_t ld, hipStream_t stream);
+
+/* T sweeps with coefficient c: per sweep, a ghost exchange of the array being
+ * read (when stale) on `comm`, then one sweep kernel per tile on `compute`.
+ * The streams may be the same. */
+sten_status sten_tiled_run(sten_tiled_handle t, int32_t T, double c, hipStream_t compute, hipStream_t comm);
+
+/* Refresh the current array's ghosts if stale (a second call in a row is skipped). */
+sten_status sten_tiled_exchange(sten_tiled_handle t, hipStream_t compute, hipStream_t comm);
+
+/* Write the current state of every tile's owned block into u (row stride ld). */
+sten_status sten_tiled_gather(sten_tiled_handle t, double* u, int64_t ld, hipStream_t stream);
+
+/* stats[0..4] = tiles, exchanges performed, exchanges skipped (epochs equal),
+ * sweep kernel launches, strips per exchange. */
+sten_status sten_tiled_stats(sten_tiled_handle t, int64_t* stats, int32_t n);
+
+/* Free the host-side handle (the workspace stays the caller's). */
+sten_status sten_tiled_destroy(sten_tiled_handle t);
+
+/* ------------------------------------------------------------------------ */
 /* Library introspection (host only; no GPU needed)                          */
 /* ------------------------------------------------------------------------ */
 

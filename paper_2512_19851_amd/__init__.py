@@ -11,6 +11,7 @@ library is missing.
 from ._lib import StenError, load  # noqa: F401
 from .ops import (  # noqa: F401
     BatchPlan,
+    TiledGrid,
     HiLoGrid,
     hilo_decode,
     hilo_encode,
@@ -22,5 +23,5 @@ from .ops import (  # noqa: F401
     sweep,
 )
 
-__all__ = ["StenError", "load", "BatchPlan", "jacobi5", "jacobi5_hilo", "jacobi5_hilo_encoded", "hilo_encode",
+__all__ = ["StenError", "load", "BatchPlan", "TiledGrid", "jacobi5", "jacobi5_hilo", "jacobi5_hilo_encoded", "hilo_encode",
            "hilo_decode", "HiLoGrid", "set_sweep_rows", "set_hilo_variant", "sweep"]

@@ -256,3 +256,69 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# Tiled execution on one GPU (chares with ghost exchange)
+# ---------------------------------------------------------------------------
+
+class TiledGrid:
+    """An H x W FP64 grid split into pr x pc tiles with depth-1 ghosts, on one GPU.
+
+    t = TiledGrid(H, W, pr, pc); t.scatter(u); t.run(T, c); u2 = t.gather()
+    `comm_stream` (optional) carries the ghost exchanges; sweeps go on the current stream.
+    """
+
+    def __init__(self, H: int, W: int, pr: int, pc: int, device=None, comm_stream=None):
+        import ctypes
+
+        lib = _lib.load()
+        self.H, self.W, self.pr, self.pc = int(H), int(W), int(pr), int(pc)
+        nbytes = int(lib.sten_tiled_workspace_bytes(self.H, self.W, self.pr, self.pc))
+        if nbytes == 0:
+            raise ValueError("invalid tiling")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device or torch.device("cuda"))
+        self.comm_stream = comm_stream
+        self._h = ctypes.c_void_p()
+        _lib.check("sten_tiled_create", lib.sten_tiled_create(self.H, self.W, self.pr, self.pc, self.ws.data_ptr(),
+                                                              nbytes, ctypes.byref(self._h)))
+
+    def _comm(self) -> int:
+        return _stream_ptr(self.comm_stream) if self.comm_stream is not None else _stream_ptr()
+
+    def scatter(self, u: torch.Tensor) -> None:
+        _check_grid(u, torch.float64, "u")
+        if tuple(u.shape) != (self.H, self.W):
+            raise ValueError("shape mismatch")
+        _lib.call("sten_tiled_scatter", self._h, u.data_ptr(), _ld(u), _stream_ptr())
+
+    def run(self, T: int, c: float = 0.25) -> None:
+        _lib.call("sten_tiled_run", self._h, int(T), float(c), _stream_ptr(), self._comm())
+
+    def exchange(self) -> None:
+        _lib.call("sten_tiled_exchange", self._h, _stream_ptr(), self._comm())
+
+    def gather(self, out: torch.Tensor | None = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty((self.H, self.W), dtype=torch.float64, device=self.ws.device)
+        _check_grid(out, torch.float64, "out")
+        _lib.call("sten_tiled_gather", self._h, out.data_ptr(), _ld(out), _stream_ptr())
+        return out
+
+    def stats(self) -> dict:
+        import ctypes
+
+        buf = (ctypes.c_int64 * 5)()
+        _lib.call("sten_tiled_stats", self._h, buf, 5)
+        return dict(zip(["tiles", "exchanges", "skipped", "sweep_launches", "strips"], list(buf)))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().sten_tiled_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -84,3 +84,13 @@ def test_validation_before_any_hip_call(lib):
     # overlapping buffers are rejected before any pointer query
     assert f(4096, 4096 + 8, 1 << 20, 4, 4, 4, 1, 0.25, None) == -2
     assert f(4096, 1 << 20, 1 << 20, 4, 4, 4, 2, 0.25, None) == -2
+
+
+def test_tiled_workspace_query(lib):
+    """Host-only layout query: valid tilings need space, invalid ones report 0."""
+    assert lib.sten_tiled_workspace_bytes(64, 64, 2, 2) > 2 * 64 * 64 * 8
+    assert lib.sten_tiled_workspace_bytes(64, 64, 65, 1) == 0
+    assert lib.sten_tiled_workspace_bytes(0, 64, 1, 1) == 0
+    one = lib.sten_tiled_workspace_bytes(100, 100, 1, 1)
+    many = lib.sten_tiled_workspace_bytes(100, 100, 4, 4)
+    assert many > one  # ghost frames and send buffers grow with the tile count
