@@ -272,6 +272,72 @@ def bench_tiled(ops, n: int, T: int, args, plain_sec_per_step: float) -> dict:
     return res
 
 
+def bench_temporal(ops, n: int, T: int, args, plain_sec_per_step: float) -> dict:
+    """The plain FP64 step with temporal blocking: `levels` sweeps per HBM pass, same bits."""
+    import torch
+
+    from workloads import large_f64
+
+    log("[bench] temporal blocking")
+    u0 = torch.from_numpy(large_f64(0, n)).to("cuda:0")
+    out = torch.empty_like(u0)
+    work = torch.empty_like(u0)
+    res = {"workload": f"{n}x{n} FP64 N(0,1) seed 0, {T} sweeps per step, bit-identical to the plain step"}
+    for levels in (2, 3, 4):
+        ops.jacobi5_tb(u0, T, levels=levels, out=out, work=work)
+        torch.cuda.synchronize()
+        reps = max(3, args.steps // 2)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ops.jacobi5_tb(u0, T, levels=levels, out=out, work=work)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / reps
+        launches = -(-T // levels)
+        res[f"levels_{levels}"] = {
+            "ms_per_step": round(sec * 1e3, 4),
+            "effective_GBps_at_16B": round(16.0 * (n - 2) ** 2 * T / sec / 1e9, 1),
+            "speedup_vs_plain": round(plain_sec_per_step / sec, 3),
+            "us_per_launch": round(sec / launches * 1e6, 2),
+            "hbm_GBps_per_launch_at_16B": round(16.0 * (n - 2) ** 2 / (sec / launches) / 1e9, 1),
+        }
+    return res
+
+
+def bench_frontend(ops, args) -> dict:
+    """One-GPU analog of the pipelining experiment (Section V): the listing program through the
+    lazy frontend, runtime against the maximum DAG depth, next to one direct call (no Python per node)."""
+    import torch
+
+    from paper_2512_19851_amd import frontend
+
+    log("[bench] frontend pipelining")
+    n, T = 4096, 200
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda:0")
+    u[0, :] = u[-1, :] = u[:, 0] = u[:, -1] = 1
+    ideal = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ops.jacobi5(u, T)
+        torch.cuda.synchronize()
+        ideal.append(time.perf_counter() - t0)
+    res = {"workload": f"listing program, {n}x{n} FP64 unit ring, {T} iterations", "ideal_ms": round(min(ideal) * 1e3, 2)}
+    for depth in (1, 10, 100, 1000):
+        ctx = frontend.Context(max_depth=depth)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u1 = ctx.create_array((n, n))
+        u2 = ctx.create_array((n, n))
+        u1[0, :] = u1[-1, :] = u1[:, 0] = u1[:, -1] = 1
+        u2[0, :] = u2[-1, :] = u2[:, 0] = u2[:, -1] = 1
+        for _ in range(T):
+            u2[1:-1, 1:-1] = 0.25 * (u1[:-2, 1:-1] + u1[2:, 1:-1] + u1[1:-1, :-2] + u1[1:-1, 2:])
+            u1, u2 = u2, u1
+        ctx.sync()
+        res[f"depth_{depth}_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+    return res
+
+
 def bench_adjoint(T: int, args) -> dict:
     """Gradient workload: 1024x1024 FP32, L = sum(w * u_T), dL/du0 and dL/dc through autograd."""
     import torch
@@ -479,6 +545,8 @@ def main() -> int:
             "mixed_hilo": bench_mixed(ops, n, T, args, sec_per_step),
             "batched": bench_batch(ops, T, args),
             "tiled": bench_tiled(ops, n, T, args, sec_per_step),
+            "temporal_blocking": bench_temporal(ops, n, T, args, sec_per_step),
+            "frontend": bench_frontend(ops, args),
             "adjoint": bench_adjoint(10, args),
         }
 

@@ -94,6 +94,27 @@ sten_status sten_sweep_f64(const double* src, double* dst, int64_t H, int64_t W,
 sten_status sten_sweep_f32(const float* src, float* dst, int64_t H, int64_t W, int64_t ld, float c,
                            hipStream_t stream);
 
+/*
+ * Temporal blocking (the same method, a different schedule): each launch
+ * applies `levels` (1..4) sweeps to a tile held in registers, so one pass over
+ * HBM serves `levels` sweeps. A tile loads its output block grown by `levels`
+ * rows and columns on every side and recomputes that halo. Bit-identical to
+ * sten_jacobi5_f64 / _f32 (same arithmetic per point and level). Needs 16-byte
+ * aligned u0/out/work and ld a multiple of 2 (FP64) or 4 (FP32), an interior
+ * and T >= 1; returns STEN_ERR_UNSUPPORTED otherwise (use the single-sweep
+ * entry points for those grids). Other errors as for sten_jacobi5_f64.
+ */
+sten_status sten_jacobi5_f64_tb(const double* u0, double* out, double* work, int64_t H, int64_t W, int64_t ld,
+                                int32_t T, double c, int32_t levels, hipStream_t stream);
+sten_status sten_jacobi5_f32_tb(const float* u0, float* out, float* work, int64_t H, int64_t W, int64_t ld,
+                                int32_t T, float c, int32_t levels, hipStream_t stream);
+
+/* Scalar slice fill (the listing's ring set-up, Section III-A): rows [r0, r1)
+ * x columns [c0, c1) of an H x W FP64 grid get `value`. STEN_ERR_ARG when the
+ * rectangle leaves the grid. */
+sten_status sten_fill_rect_f64(double* grid, int64_t H, int64_t W, int64_t ld, int64_t r0, int64_t r1,
+                               int64_t c0, int64_t c1, double value, hipStream_t stream);
+
 /* Tuning hook: output rows per workgroup tile of the sweep kernels (4, 8 or
  * 16; 0 restores the built-in choice). Process-wide; not thread-safe against
  * concurrent launches. STEN_ERR_ARG for other values. */
@@ -213,7 +234,8 @@ sten_status sten_batch_run(sten_batch_handle plan, hipStream_t stream);
 
 /* Autotuner: time every candidate configuration (block 256/512/1024 x LDS
  * budget 32/64/80/160 KiB within the device limit) on this batch, `reps`
- * runs each with HIP events (synchronises `stream`), keep the fastest in the
+ * runs each with HIP events (synchronises `stream`), each with the
+ * register-resident mode on and off, keep the fastest in the
  * plan, report its time per run in *best_us (may be NULL) and append it to
  * the cache file (when the path is not NULL) for later sten_batch_plan calls.
  * Overwrites the grids' outputs. */
@@ -226,8 +248,16 @@ sten_status sten_batch_autotune(sten_batch_handle plan, const char* tune_cache_p
 sten_status sten_batch_configure(sten_batch_handle plan, int32_t block, int32_t lds_bytes, int32_t wg_per_cu,
                                  hipStream_t stream);
 
+/* Switch the register-resident mode on (1) or off (0) and re-classify the
+ * grids. In that mode a workgroup holds the whole grid in registers (lanes
+ * take columns, waves take row bands of at most 64 rows) and exchanges only
+ * band-edge rows and wave-edge columns through LDS; it applies to grids with
+ * ceil(W/64) <= waves per workgroup and enough bands for the rows. */
+sten_status sten_batch_set_modes(sten_batch_handle plan, int32_t use_reg, hipStream_t stream);
+
 /* Plan introspection: info[0..6] = block, LDS bytes, workgroups per CU, grid
- * size, grids kept in LDS, grids swept in global memory, grids only copied. */
+ * size, grids kept in LDS, grids swept in global memory, grids only copied;
+ * with n >= 9 also info[7] = grids held in registers, info[8] = register mode on. */
 sten_status sten_batch_plan_info(sten_batch_handle plan, int32_t* info, int32_t n);
 
 /* Free the host-side plan (device workspace stays the caller's). */
@@ -321,6 +351,38 @@ sten_status sten_tiled_stats(sten_tiled_handle t, int64_t* stats, int32_t n);
 
 /* Free the host-side handle (the workspace stays the caller's). */
 sten_status sten_tiled_destroy(sten_tiled_handle t);
+
+/* ------------------------------------------------------------------------ */
+/* General star stencils with node fusion                                    */
+/* ------------------------------------------------------------------------ */
+/*
+ * The class of slice expressions the paper's backend turns into kernels
+ * (Section III-C): a constant-coefficient star stencil of radius R (1..4),
+ *     out[i,j] = c0*A[i,j] + sum_{k=1..R} (cn[k-1]*A[i-k,j] + cs[k-1]*A[i+k,j]
+ *                                         + cw[k-1]*A[i,j-k] + ce[k-1]*A[i,j+k])
+ * evaluated left to right in that order, each product rounded then added (no
+ * fused multiply-add), on points at least R away from every edge; the frame of
+ * width R is not written. Ghost depth = R. Bit-identical to that expression
+ * evaluated in FP64.
+ */
+typedef struct {
+    int32_t radius;   /* 1..4 */
+    int32_t reserved;
+    double c0;
+    double cn[4], cs[4], cw[4], ce[4];  /* entries past the radius are ignored */
+} sten_star_coef;
+
+/* Node fusion (Section III-B): nout (1..4) stencils of the same radius applied
+ * to the same input in one kernel, which reads `in` once. outs: host array of
+ * nout device pointers (grids of the same H, W, ld). STEN_ERR_ARG when radii
+ * differ or are out of range; STEN_ERR_ALIAS when any two grids overlap. */
+sten_status sten_star_f64(const double* in, double* const* outs, const sten_star_coef* coefs, int32_t nout,
+                          int64_t H, int64_t W, int64_t ld, hipStream_t stream);
+
+/* T applications of one star stencil with a ping-pong swap: out (and work,
+ * needed when T >= 2) start as copies of u0, so the frame stays u0's. */
+sten_status sten_star_iterate_f64(const double* u0, double* out, double* work, const sten_star_coef* coef,
+                                  int64_t H, int64_t W, int64_t ld, int32_t T, hipStream_t stream);
 
 /* ------------------------------------------------------------------------ */
 /* Library introspection (host only; no GPU needed)                          */

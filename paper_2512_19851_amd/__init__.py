@@ -16,12 +16,15 @@ from .ops import (  # noqa: F401
     hilo_decode,
     hilo_encode,
     jacobi5,
+    jacobi5_tb,
     jacobi5_hilo,
     jacobi5_hilo_encoded,
     set_hilo_variant,
     set_sweep_rows,
+    star,
+    star_iterate,
     sweep,
 )
 
-__all__ = ["StenError", "load", "BatchPlan", "TiledGrid", "jacobi5", "jacobi5_hilo", "jacobi5_hilo_encoded", "hilo_encode",
-           "hilo_decode", "HiLoGrid", "set_sweep_rows", "set_hilo_variant", "sweep"]
+__all__ = ["StenError", "load", "BatchPlan", "TiledGrid", "jacobi5", "jacobi5_tb", "jacobi5_hilo", "jacobi5_hilo_encoded", "hilo_encode",
+           "hilo_decode", "HiLoGrid", "set_sweep_rows", "set_hilo_variant", "sweep", "star", "star_iterate"]

@@ -59,6 +59,9 @@ SIGNATURES = {
     "sten_tune_sweep_rows": (ctypes.c_int, [_i32]),
     "sten_sweep_f64": (ctypes.c_int, [_vp, _vp, _i64, _i64, _i64, _f64, _vp]),
     "sten_sweep_f32": (ctypes.c_int, [_vp, _vp, _i64, _i64, _i64, _f32, _vp]),
+    "sten_fill_rect_f64": (ctypes.c_int, [_vp, _i64, _i64, _i64, _i64, _i64, _i64, _i64, _f64, _vp]),
+    "sten_jacobi5_f64_tb": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, _i64, _i32, _f64, _i32, _vp]),
+    "sten_jacobi5_f32_tb": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, _i64, _i32, _f32, _i32, _vp]),
     "sten_hilo_bytes": (_sz, [_i64, _i64]),
     "sten_jacobi5_f64_hilo_work_bytes": (_sz, [_i64, _i64]),
     "sten_hilo_encode": (ctypes.c_int, [_vp, _vp, _i64, _i64, _i64, _vp]),
@@ -73,6 +76,7 @@ SIGNATURES = {
     "sten_batch_autotune": (ctypes.c_int, [_vp, ctypes.c_char_p, _i32, ctypes.POINTER(_f32), _vp]),
     "sten_batch_plan_info": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), _i32]),
     "sten_batch_configure": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp]),
+    "sten_batch_set_modes": (ctypes.c_int, [_vp, _i32, _vp]),
     "sten_batch_destroy": (ctypes.c_int, [_vp]),
     "sten_adjoint_partials_len": (_sz, [_i64, _i64]),
     "sten_jacobi5_f32_states": (ctypes.c_int, [_vp, _vp, _i64, _i64, _i64, _i32, _f32, _vp]),
@@ -88,7 +92,16 @@ SIGNATURES = {
     "sten_tiled_gather": (ctypes.c_int, [_vp, _vp, _i64, _vp]),
     "sten_tiled_stats": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64), _i32]),
     "sten_tiled_destroy": (ctypes.c_int, [_vp]),
+    "sten_star_f64": (ctypes.c_int, [_vp, _vp, _vp, _i32, _i64, _i64, _i64, _vp]),
+    "sten_star_iterate_f64": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _i64, _i64, _i32, _vp]),
 }
+
+
+class StarCoefC(ctypes.Structure):
+    """Mirror of sten_star_coef in include/sten.h."""
+
+    _fields_ = [("radius", _i32), ("reserved", _i32), ("c0", _f64), ("cn", _f64 * 4), ("cs", _f64 * 4),
+                ("cw", _f64 * 4), ("ce", _f64 * 4)]
 
 
 class StenInst(ctypes.Structure):

@@ -34,7 +34,8 @@
 namespace sten {
 namespace {
 
-enum : int32_t { MODE_COPY = 0, MODE_LDS = 1, MODE_GLOBAL = 2 };
+enum : int32_t { MODE_COPY = 0, MODE_LDS = 1, MODE_GLOBAL = 2, MODE_REG = 3 };
+
 
 struct alignas(16) Desc {
     const float* u0;
@@ -76,7 +77,7 @@ __device__ __forceinline__ float stencil(float n, float s, float w, float e, flo
     return c * t;
 }
 
-__device__ void run_copy(const Desc& d) {
+__device__ __forceinline__ void run_copy(const Desc& d) {
     const int n = d.H * d.W;
     for (int p = threadIdx.x; p < n; p += blockDim.x) {
         const int i = p / d.W;
@@ -86,7 +87,7 @@ __device__ void run_copy(const Desc& d) {
 }
 
 // T sweeps with both buffers in LDS (packed rows, stride W).
-__device__ void run_lds(const Desc& d, int T, float c, float* lds) {
+__device__ __forceinline__ void run_lds(const Desc& d, int T, float c, float* lds) {
     const int H = d.H, W = d.W;
     const int n = H * W;
     float* A = lds;
@@ -122,7 +123,7 @@ __device__ void run_lds(const Desc& d, int T, float c, float* lds) {
 }
 
 // T sweeps between the grid's out and work buffers in global memory.
-__device__ void run_global(const Desc& d, int T, float c) {
+__device__ __forceinline__ void run_global(const Desc& d, int T, float c) {
     const int H = d.H, W = d.W;
     const int64_t ld = d.ld;
     // ring of u0 into out (and work when it is written)
@@ -161,6 +162,142 @@ __device__ void run_global(const Desc& d, int T, float c) {
     }
 }
 
+// Register-resident sweeps: the whole grid lives in registers for all T sweeps.
+// Each lane holds V consecutive columns (64*V >= W, so one wave spans a whole
+// row) of R consecutive rows; wave w holds rows [w*R, w*R + R). Up/down
+// neighbours come from the lane's own registers; left/right neighbours from
+// its own registers or, for its first and last column, from the adjacent
+// lane by a DPP wave shift (the last column of the grid is the ring, so no
+// wave ever needs a column from another wave). Only each wave's first and
+// last row cross to other waves, through a double-buffered LDS area (parity =
+// sweep mod 2), so one workgroup barrier per sweep suffices. Rows are updated
+// in order with the previous row's old values kept in `prev` (in-place
+// rolling update). Rows past the grid are dummies: loaded as 0, never
+// computed, never stored.
+constexpr int kRegVs[3] = {1, 2, 4};
+constexpr int kRegRs[5] = {1, 2, 4, 8, 16};
+
+struct RegShape {
+    int V, R;  // columns and rows per lane (0: the grid does not fit)
+};
+
+__device__ __host__ inline RegShape reg_shape(int H, int W, int block) {
+    const int nw = block / 64;
+    RegShape s{0, 0};
+    for (int v : kRegVs) {
+        if (64 * v < W) continue;
+        for (int r : kRegRs) {
+            if (nw * r >= H && v * r <= 64) {
+                s.V = v;
+                s.R = r;
+                return s;
+            }
+        }
+        break;
+    }
+    return s;
+}
+
+// LDS floats of the row exchange area (both parities, first and last row of every wave).
+__device__ __host__ inline int reg_lds_floats(const RegShape& s, int block) { return 2 * 2 * (block / 64) * 64 * s.V; }
+
+__device__ __forceinline__ float dpp_from_lower_lane(float v) {  // lane l receives lane l-1
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xF, 0xF,
+                                                                 false));
+}
+__device__ __forceinline__ float dpp_from_upper_lane(float v) {  // lane l receives lane l+1
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xF, 0xF,
+                                                                 false));
+}
+
+template <int V, int R>
+__device__ __forceinline__ void run_reg(const Desc& d, int T, float c, float* lds) {
+    const int H = d.H, W = d.W;
+    const int64_t ld = d.ld;
+    const int nw = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int i0 = wave * R;
+    const int j0 = lane * V;
+    const int rowf = 64 * V;       // floats of one published row
+    const int half = 2 * nw * rowf;
+    // published slots: first row of wave w at [w*rowf], last row at [(nw + w)*rowf]
+    const int o_first = wave * rowf + j0;
+    const int o_last = (nw + wave) * rowf + j0;
+    const int o_above = (nw + wave - 1) * rowf + j0;  // last row of the wave above
+    const int o_below = (wave + 1) * rowf + j0;       // first row of the wave below
+    bool col_in[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) col_in[e] = (j0 + e >= 1) && (j0 + e <= W - 2);
+
+    float v[R][V];
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+            v[k][e] = (i0 + k < H && j0 + e < W) ? d.u0[(int64_t)(i0 + k) * ld + j0 + e] : 0.0f;
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+        lds[o_first + e] = v[0][e];
+        lds[o_last + e] = v[R - 1][e];
+    }
+    __syncthreads();
+    for (int t = 0; t < T; ++t) {
+        const float* cur_h = lds + (t & 1) * half;
+        float* nxt_h = lds + ((t + 1) & 1) * half;
+        float prev[V], below[V];
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            prev[e] = (wave > 0) ? cur_h[o_above + e] : 0.0f;
+            below[e] = (wave + 1 < nw) ? cur_h[o_below + e] : 0.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int i = i0 + k;
+            const bool row_in = (i >= 1) && (i <= H - 2);
+            const float lft = dpp_from_lower_lane(v[k][V - 1]);  // column j0 - 1
+            const float rgt = dpp_from_upper_lane(v[k][0]);      // column j0 + V
+            float nv[V];
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const float dn = (k == R - 1) ? below[e] : v[k + 1 < R ? k + 1 : k][e];
+                const float w_ = (e == 0) ? lft : v[k][e > 0 ? e - 1 : 0];
+                const float e_ = (e == V - 1) ? rgt : v[k][e < V - 1 ? e + 1 : 0];
+                nv[e] = (row_in && col_in[e]) ? stencil(prev[e], dn, w_, e_, c) : v[k][e];
+            }
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                prev[e] = v[k][e];
+                v[k][e] = nv[e];
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            nxt_h[o_first + e] = v[0][e];
+            nxt_h[o_last + e] = v[R - 1][e];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+            if (i0 + k < H && j0 + e < W) d.out[(int64_t)(i0 + k) * ld + j0 + e] = v[k][e];
+}
+
+__device__ __forceinline__ void run_reg_any(const Desc& d, int T, float c, float* lds, int code) {
+    // code = V * 32 + R
+    switch (code) {
+#define STEN_REG_CASE(V_, R_) \
+    case V_ * 32 + R_: run_reg<V_, R_>(d, T, c, lds); break;
+        STEN_REG_CASE(1, 1) STEN_REG_CASE(1, 2) STEN_REG_CASE(1, 4) STEN_REG_CASE(1, 8) STEN_REG_CASE(1, 16)
+        STEN_REG_CASE(2, 1) STEN_REG_CASE(2, 2) STEN_REG_CASE(2, 4) STEN_REG_CASE(2, 8) STEN_REG_CASE(2, 16)
+        STEN_REG_CASE(4, 1) STEN_REG_CASE(4, 2) STEN_REG_CASE(4, 4) STEN_REG_CASE(4, 8) STEN_REG_CASE(4, 16)
+#undef STEN_REG_CASE
+        default: break;
+    }
+}
+
 __global__ void batch_reset_kernel(uint32_t* counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
 }
@@ -176,7 +313,9 @@ __global__ void batch_kernel(const Desc* __restrict__ descs, uint32_t* __restric
         __syncthreads();
         if (idx >= count) break;  // every workgroup reaches this once the queue is drained
         const Desc d = descs[idx];
-        if (d.mode == MODE_LDS)
+        if ((d.mode & 0xFF) == MODE_REG)
+            run_reg_any(d, T, c, lds, d.mode >> 8);
+        else if (d.mode == MODE_LDS)
             run_lds(d, T, c, lds);
         else if (d.mode == MODE_GLOBAL)
             run_global(d, T, c);
@@ -187,9 +326,10 @@ __global__ void batch_kernel(const Desc* __restrict__ descs, uint32_t* __restric
 }
 
 struct Config {
-    int block = 512;
+    int block = 1024;
     int lds_bytes = 160 * 1024;  // clamped to the device limit at plan time
     int wg_per_cu = 1;
+    int use_reg = 1;             // register-resident mode for grids that fit
 };
 
 }  // namespace
@@ -201,7 +341,7 @@ struct sten_batch_plan_s {
     float c = 0.25f;
     sten::Config cfg;
     int grid = 0;
-    int n_lds = 0, n_global = 0, n_copy = 0;
+    int n_lds = 0, n_global = 0, n_copy = 0, n_reg = 0;
     sten::Desc* d_descs = nullptr;
     uint32_t* d_counter = nullptr;
     std::vector<sten::Desc> h_descs;
@@ -238,8 +378,8 @@ bool cache_lookup(const char* path, const std::string& key, Config& cfg) {
         const size_t sp = line.find(' ');
         if (sp == std::string::npos || line.substr(0, sp) != key) continue;
         Config c2;
-        if (sscanf(line.c_str() + sp + 1, "block=%d lds_bytes=%d wg_per_cu=%d", &c2.block, &c2.lds_bytes,
-                   &c2.wg_per_cu) == 3) {
+        if (sscanf(line.c_str() + sp + 1, "block=%d lds_bytes=%d wg_per_cu=%d use_reg=%d", &c2.block,
+                   &c2.lds_bytes, &c2.wg_per_cu, &c2.use_reg) == 4) {
             cfg = c2;
             found = true;
         }
@@ -253,7 +393,7 @@ bool cache_store(const char* path, const std::string& key, const Config& cfg, fl
     std::ofstream f(path, std::ios::app);
     if (!f) return false;
     f << key << " block=" << cfg.block << " lds_bytes=" << cfg.lds_bytes << " wg_per_cu=" << cfg.wg_per_cu
-      << " us=" << us << "\n";
+      << " use_reg=" << cfg.use_reg << " us=" << us << "\n";
     return (bool)f;
 }
 
@@ -299,14 +439,18 @@ void build_descs(sten_batch_plan_s* p) {
     };
     std::vector<Item> items;
     items.reserve(p->count);
-    p->n_lds = p->n_global = p->n_copy = 0;
+    p->n_lds = p->n_global = p->n_copy = p->n_reg = 0;
     for (const sten_inst& s : p->h_insts) {
         if (s.H == 0 || s.W == 0) continue;
         Desc d{s.u0, s.out, s.work, s.H, s.W, s.ld, MODE_COPY};
         double cost = (double)s.H * s.W;
         if (s.H >= 3 && s.W >= 3 && p->T > 0) {
             const double pts = (double)(s.H - 2) * (s.W - 2) * p->T;
-            if (2 * s.H * s.W <= lds_floats) {
+            const RegShape rs = reg_shape(s.H, s.W, p->cfg.block);
+            if (p->cfg.use_reg && rs.V > 0 && reg_lds_floats(rs, p->cfg.block) <= lds_floats) {
+                d.mode = MODE_REG | ((rs.V * 32 + rs.R) << 8);
+                cost = 0.3 * p->T * (double)(p->cfg.block / 64) * rs.R * 64 * rs.V;  // lane-points swept
+            } else if (2 * s.H * s.W <= lds_floats) {
                 d.mode = MODE_LDS;
                 cost = pts + 2.0 * s.H * s.W;
             } else {
@@ -314,7 +458,8 @@ void build_descs(sten_batch_plan_s* p) {
                 cost = 2.5 * pts;  // global sweeps move about 2.5x the bytes of LDS sweeps per point
             }
         }
-        if (d.mode == MODE_LDS) ++p->n_lds;
+        if ((d.mode & 0xFF) == MODE_REG) ++p->n_reg;
+        else if (d.mode == MODE_LDS) ++p->n_lds;
         else if (d.mode == MODE_GLOBAL) ++p->n_global;
         else ++p->n_copy;
         items.push_back({d, cost});
@@ -416,6 +561,18 @@ sten_status sten_batch_destroy(sten_batch_handle plan) {
     return STEN_OK;
 }
 
+sten_status sten_batch_set_modes(sten_batch_handle plan, int32_t use_reg, hipStream_t stream) {
+    if (plan == nullptr || (use_reg != 0 && use_reg != 1)) return STEN_ERR_ARG;
+    const sten::Config saved = plan->cfg;
+    plan->cfg.use_reg = use_reg;
+    sten_status st = sten::finalize_plan(plan, stream);
+    if (st != STEN_OK) {
+        plan->cfg = saved;
+        (void)sten::finalize_plan(plan, stream);
+    }
+    return st;
+}
+
 sten_status sten_batch_plan_info(sten_batch_handle plan, int32_t* info, int32_t n) {
     if (plan == nullptr || info == nullptr || n < 7) return STEN_ERR_ARG;
     info[0] = plan->cfg.block;
@@ -425,6 +582,10 @@ sten_status sten_batch_plan_info(sten_batch_handle plan, int32_t* info, int32_t 
     info[4] = plan->n_lds;
     info[5] = plan->n_global;
     info[6] = plan->n_copy;
+    if (n >= 9) {
+        info[7] = plan->n_reg;
+        info[8] = plan->cfg.use_reg;
+    }
     return STEN_OK;
 }
 
@@ -438,6 +599,7 @@ sten_status sten_batch_configure(sten_batch_handle plan, int32_t block, int32_t 
     c.block = block;
     c.lds_bytes = lds_bytes;
     c.wg_per_cu = wg_per_cu;
+    c.use_reg = plan->cfg.use_reg;
     const Config saved = plan->cfg;
     plan->cfg = c;
     sten_status st = finalize_plan(plan, stream);
@@ -454,14 +616,17 @@ sten_status sten_batch_autotune(sten_batch_handle plan, const char* tune_cache_p
     if (plan == nullptr || reps < 1) return STEN_ERR_ARG;
     const int limit = device_lds_limit();
     std::vector<Config> cands;
-    for (int block : {256, 512, 1024}) {
-        for (int kb : {32, 64, 80, 160}) {
-            if (kb * 1024 > limit) continue;
-            Config c;
-            c.block = block;
-            c.lds_bytes = kb * 1024;
-            c.wg_per_cu = std::max(1, std::min(limit / (kb * 1024), 2048 / block));
-            cands.push_back(c);
+    for (int use_reg : {1, 0}) {
+        for (int block : {256, 512, 1024}) {
+            for (int kb : {32, 64, 80, 160}) {
+                if (kb * 1024 > limit) continue;
+                Config c;
+                c.block = block;
+                c.lds_bytes = kb * 1024;
+                c.wg_per_cu = std::max(1, std::min(limit / (kb * 1024), 2048 / block));
+                c.use_reg = use_reg;
+                cands.push_back(c);
+            }
         }
     }
     hipEvent_t e0, e1;

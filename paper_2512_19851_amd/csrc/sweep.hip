@@ -186,6 +186,18 @@ __global__ void ring_copy_kernel(const T* __restrict__ u0, T* __restrict__ d1, T
     if (d2 != nullptr) d2[off] = v;
 }
 
+// Fill rows [r0, r1) x columns [c0, c1) of a grid with one value.
+__global__ void fill_rect_kernel(double* __restrict__ p, int64_t ld, int r0, int r1, int c0, int c1, double v) {
+    const int64_t w = c1 - c0;
+    const int64_t total = (int64_t)(r1 - r0) * w;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx / w;
+        const int64_t j = idx - i * w;
+        p[(r0 + i) * ld + c0 + j] = v;
+    }
+}
+
 // Plain 2-D copy of an H x W grid (degenerate calls: T = 0 or empty interior).
 template <typename T>
 __global__ void copy_kernel(const T* __restrict__ src, T* __restrict__ dst, int H, int W, int64_t ld) {
@@ -290,6 +302,20 @@ void launch_sweep_f32_internal(const float* in, float* out, int H, int W, int64_
 }  // namespace sten
 
 extern "C" {
+
+sten_status sten_fill_rect_f64(double* grid, int64_t H, int64_t W, int64_t ld, int64_t r0, int64_t r1,
+                               int64_t c0, int64_t c1, double value, hipStream_t stream) {
+    using namespace sten;
+    if (H < 0 || W < 0 || (H > 0 && ld < W) || H > INT32_MAX / 2 || W > INT32_MAX / 2) return STEN_ERR_ARG;
+    if (r0 < 0 || c0 < 0 || r1 > H || c1 > W || r0 > r1 || c0 > c1) return STEN_ERR_ARG;
+    if (r0 == r1 || c0 == c1) return STEN_OK;
+    if (grid == nullptr) return STEN_ERR_PTR;
+    if (!is_device_ptr(grid)) return STEN_ERR_PTR;
+    const int64_t total = (r1 - r0) * (c1 - c0);
+    const uint32_t blocks = (uint32_t)std::min<int64_t>((total + 255) / 256, 65536);
+    fill_rect_kernel<<<blocks, 256, 0, stream>>>(grid, ld, (int)r0, (int)r1, (int)c0, (int)c1, value);
+    return check_launch();
+}
 
 sten_status sten_sweep_f64(const double* src, double* dst, int64_t H, int64_t W, int64_t ld, double c,
                            hipStream_t stream) {

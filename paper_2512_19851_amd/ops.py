@@ -67,6 +67,30 @@ def jacobi5(u0: torch.Tensor, T: int, c: float = 0.25, out: torch.Tensor | None 
     return out
 
 
+def jacobi5_tb(u0: torch.Tensor, T: int, c: float = 0.25, levels: int = 2, out: torch.Tensor | None = None,
+               work: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Temporally blocked method: `levels` sweeps per HBM pass, bit-identical to `jacobi5`.
+
+    Grids the blocked kernels do not handle (misaligned, no interior, T = 0) go
+    through the single-sweep path.
+    """
+    fn = {torch.float64: "sten_jacobi5_f64_tb", torch.float32: "sten_jacobi5_f32_tb"}.get(u0.dtype)
+    if fn is None:
+        raise TypeError("u0 must be float32 or float64")
+    _check_grid(u0, u0.dtype, "u0")
+    H, W = u0.shape
+    if out is None:
+        out = torch.empty_strided(u0.shape, u0.stride(), dtype=u0.dtype, device=u0.device)
+    if work is None and T > levels and H >= 3 and W >= 3:
+        work = torch.empty_strided(u0.shape, u0.stride(), dtype=u0.dtype, device=u0.device)
+    code = getattr(_lib.load(), fn)(u0.data_ptr(), out.data_ptr(), work.data_ptr() if work is not None else None,
+                                    H, W, _ld(u0), int(T), float(c), int(levels), _stream_ptr(stream))
+    if code == -6:
+        return jacobi5(u0, T, c, out=out, work=work, stream=stream)
+    _lib.check(fn, code)
+    return out
+
+
 def sweep(src: torch.Tensor, dst: torch.Tensor, c: float = 0.25, stream=None) -> torch.Tensor:
     """One sweep: dst's interior from src (dst's ring untouched); returns dst."""
     fn = {torch.float64: "sten_sweep_f64", torch.float32: "sten_sweep_f32"}.get(src.dtype)
@@ -238,12 +262,16 @@ class BatchPlan:
         _lib.call("sten_batch_configure", self._handle, int(block), int(lds_bytes), int(wg_per_cu),
                   _stream_ptr(stream))
 
+    def set_register_mode(self, on: bool, stream=None) -> None:
+        """Register-resident mode for grids that fit (on by default)."""
+        _lib.call("sten_batch_set_modes", self._handle, 1 if on else 0, _stream_ptr(stream))
+
     def info(self) -> dict:
         import ctypes
 
-        buf = (ctypes.c_int32 * 7)()
-        _lib.call("sten_batch_plan_info", self._handle, buf, 7)
-        keys = ["block", "lds_bytes", "wg_per_cu", "grid", "n_lds", "n_global", "n_copy"]
+        buf = (ctypes.c_int32 * 9)()
+        _lib.call("sten_batch_plan_info", self._handle, buf, 9)
+        keys = ["block", "lds_bytes", "wg_per_cu", "grid", "n_lds", "n_global", "n_copy", "n_reg", "use_reg"]
         return dict(zip(keys, list(buf)))
 
     def close(self) -> None:
@@ -322,3 +350,55 @@ class TiledGrid:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# General star stencils with node fusion
+# ---------------------------------------------------------------------------
+
+def _star_coef(spec):
+    """spec = (c0, cn, cs, cw, ce) with four equal-length lists (the radius)."""
+    c0, cn, cs, cw, ce = spec
+    R = len(cn)
+    if not (1 <= R <= 4 and len(cs) == len(cw) == len(ce) == R):
+        raise ValueError("a star stencil needs radius 1..4 and four lists of that length")
+    s = _lib.StarCoefC()
+    s.radius = R
+    s.c0 = float(c0)
+    for k in range(R):
+        s.cn[k], s.cs[k], s.cw[k], s.ce[k] = float(cn[k]), float(cs[k]), float(cw[k]), float(ce[k])
+    return s
+
+
+def star(u: torch.Tensor, specs, outs=None, stream=None) -> list:
+    """Apply 1..4 star stencils of one radius to u in one fused kernel; returns the outputs.
+
+    Each output starts as a copy of u (so its frame of width R is u's) unless `outs` is given.
+    """
+    import ctypes
+
+    _check_grid(u, torch.float64, "u")
+    specs = list(specs)
+    if outs is None:
+        outs = [u.clone() for _ in specs]
+    coefs = (_lib.StarCoefC * len(specs))(*[_star_coef(sp) for sp in specs])
+    ptrs = (ctypes.c_void_p * len(specs))(*[o.data_ptr() for o in outs])
+    H, W = u.shape
+    _lib.call("sten_star_f64", u.data_ptr(), ctypes.cast(ptrs, ctypes.c_void_p), ctypes.cast(coefs, ctypes.c_void_p),
+              len(specs), H, W, _ld(u), _stream_ptr(stream))
+    return outs
+
+
+def star_iterate(u0: torch.Tensor, T: int, spec, out=None, work=None, stream=None) -> torch.Tensor:
+    """T applications of one star stencil with a ping-pong swap."""
+    import ctypes
+
+    _check_grid(u0, torch.float64, "u0")
+    coef = _star_coef(spec)
+    out = out if out is not None else torch.empty_like(u0)
+    if work is None and T >= 2:
+        work = torch.empty_like(u0)
+    H, W = u0.shape
+    _lib.call("sten_star_iterate_f64", u0.data_ptr(), out.data_ptr(), work.data_ptr() if work is not None else None,
+              ctypes.cast(ctypes.pointer(coef), ctypes.c_void_p), H, W, _ld(u0), int(T), _stream_ptr(stream))
+    return out

@@ -1,0 +1,161 @@
+"""The lazy frontend's host logic: ASTs, the in-place rule, the DAG, flushing and fusion (CPU).
+
+A recording backend executes each node with plain NumPy slicing, so the
+frontend's semantics can be checked against running the same program
+eagerly in NumPy, without a GPU.
+"""
+
+import numpy as np
+import pytest
+
+from paper_2512_19851_amd import frontend as fe
+
+
+class NumpyBackend:
+    """Executes nodes eagerly in NumPy and records the launch groups."""
+
+    def __init__(self):
+        self.groups = []
+
+    def alloc(self, shape):
+        return np.zeros(shape)
+
+    def fusable(self, a, b):
+        sa, sb = fe.match_star(a), fe.match_star(b)
+        return sa is not None and sb is not None and sa[0] is sb[0] and len(sa[1][1]) == len(sb[1][1])
+
+    def _eval(self, e):
+        if isinstance(e, fe.Const):
+            return e.value
+        if isinstance(e, fe.Ref):
+            r0, r1, c0, c1 = e.region
+            return e.array.data[r0:r1, c0:c1].copy()
+        a, b = self._eval(e.a), self._eval(e.b)
+        return {"+": lambda: a + b, "-": lambda: a - b, "*": lambda: a * b}[e.op]()
+
+    def run(self, group):
+        self.groups.append([(n.ast, fe.match_jacobi(n) is not None, fe.match_star(n) is not None) for n in group])
+        vals = [self._eval(n.expr) for n in group]  # fused nodes read before any writes
+        for n, v in zip(group, vals):
+            r0, r1, c0, c1 = n.region
+            n.out.data[r0:r1, c0:c1] = v
+
+    def synchronize(self):
+        pass
+
+
+def listing(ctx, H, W, T):
+    u1 = ctx.create_array((H, W))
+    u2 = ctx.create_array((H, W))
+    u1[0, :] = u1[-1, :] = u1[:, 0] = u1[:, -1] = 1
+    u2[0, :] = u2[-1, :] = u2[:, 0] = u2[:, -1] = 1
+    for _ in range(T):
+        u2[1:-1, 1:-1] = 0.25 * (u1[:-2, 1:-1] + u1[2:, 1:-1] + u1[1:-1, :-2] + u1[1:-1, 2:])
+        u1, u2 = u2, u1
+    ctx.sync()
+    return u1
+
+
+def numpy_listing(H, W, T):
+    u1 = np.zeros((H, W))
+    u2 = np.zeros((H, W))
+    for u in (u1, u2):
+        u[0, :] = u[-1, :] = u[:, 0] = u[:, -1] = 1
+    for _ in range(T):
+        u2[1:-1, 1:-1] = 0.25 * (u1[:-2, 1:-1] + u1[2:, 1:-1] + u1[1:-1, :-2] + u1[1:-1, 2:])
+        u1, u2 = u2, u1
+    return u1
+
+
+@pytest.mark.parametrize("depth", [1, 3, 7, 1000])
+def test_listing_program_semantics(depth):
+    be = NumpyBackend()
+    ctx = fe.Context(max_depth=depth, backend=be)
+    u = listing(ctx, 9, 12, 10)
+    assert np.array_equal(u.data, numpy_listing(9, 12, 10))
+    # the ten iterations share one parameterised AST; the eight fills share another
+    assert ctx.distinct_asts() == 2
+    assert ctx.stats["nodes"] == 8 + 10
+    assert all(j for g in be.groups for (_, j, _) in g if "*" in g[0][0])
+
+
+def test_in_place_assignment_rejected():
+    ctx = fe.Context(backend=NumpyBackend())
+    a = ctx.create_array((6, 6))
+    with pytest.raises(fe.InPlaceDependencyError):
+        a[1:-1, 1:-1] = 0.25 * (a[:-2, 1:-1] + a[2:, 1:-1] + a[1:-1, :-2] + a[1:-1, 2:])
+
+
+def test_dag_depth_and_flush_policy():
+    be = NumpyBackend()
+    ctx = fe.Context(max_depth=4, backend=be)
+    a = ctx.create_array((8, 8))
+    b = ctx.create_array((8, 8))
+    a[0, :] = 1        # depth 1
+    b[0, :] = 2        # independent of a: depth 1
+    assert ctx.depth() == 1
+    b[1:-1, 1:-1] = 0.25 * (a[:-2, 1:-1] + a[2:, 1:-1] + a[1:-1, :-2] + a[1:-1, 2:])  # true dep on a, output dep on b
+    assert ctx.depth() == 2
+    a[1:-1, 1:-1] = 0.25 * (b[:-2, 1:-1] + b[2:, 1:-1] + b[1:-1, :-2] + b[1:-1, 2:])  # true + anti: depth 3
+    assert ctx.depth() == 3 and ctx.stats["flushes"] == 0
+    b[1:-1, 1:-1] = 0.25 * (a[:-2, 1:-1] + a[2:, 1:-1] + a[1:-1, :-2] + a[1:-1, 2:])  # depth 4
+    b[2, 2] = 5.0  # would be depth 5 > max: the DAG is flushed first
+    assert ctx.stats["flushes"] == 1 and ctx.depth() == 1
+    ctx.sync()
+    assert ctx.stats["flushes"] == 2
+
+
+def test_fusion_of_independent_star_nodes():
+    be = NumpyBackend()
+    ctx = fe.Context(backend=be)
+    a = ctx.create_array((12, 14))
+    a[:, :] = 1.5
+    b = ctx.create_array((12, 14))
+    c = ctx.create_array((12, 14))
+    s1 = 0.5 * a[1:-1, 1:-1] + 0.25 * a[:-2, 1:-1] + 0.125 * a[2:, 1:-1] + 0.0625 * a[1:-1, :-2] + 2.0 * a[1:-1, 2:]
+    b[1:-1, 1:-1] = s1
+    c[1:-1, 1:-1] = -1.0 * a[1:-1, 1:-1] + 1.0 * a[:-2, 1:-1] + 1.0 * a[2:, 1:-1] + 1.0 * a[1:-1, :-2] + 1.0 * a[1:-1, 2:]
+    ctx.sync()
+    sizes = [len(g) for g in be.groups]
+    assert sizes == [1, 2]  # the fill, then b and c fused (same shape, no path between them)
+    assert ctx.stats["fused_nodes"] == 2
+    ref = np.full((12, 14), 1.5)
+    want_b = np.zeros((12, 14))
+    want_b[1:-1, 1:-1] = 0.5 * ref[1:-1, 1:-1] + 0.25 * ref[:-2, 1:-1] + 0.125 * ref[2:, 1:-1] + \
+        0.0625 * ref[1:-1, :-2] + 2.0 * ref[1:-1, 2:]
+    assert np.array_equal(b.data, want_b)
+
+
+def test_dependent_nodes_not_fused():
+    be = NumpyBackend()
+    ctx = fe.Context(backend=be)
+    a = ctx.create_array((10, 10))
+    b = ctx.create_array((10, 10))
+    c = ctx.create_array((10, 10))
+    star = lambda x: (0.5 * x[1:-1, 1:-1] + 0.25 * x[:-2, 1:-1] + 0.25 * x[2:, 1:-1]  # noqa: E731
+                      + 0.25 * x[1:-1, :-2] + 0.25 * x[1:-1, 2:])
+    b[1:-1, 1:-1] = star(a)
+    c[1:-1, 1:-1] = star(b)  # reads b: a path b -> c, so no fusion
+    ctx.sync()
+    assert [len(g) for g in be.groups] == [1, 1]
+
+
+def test_pattern_matchers():
+    ctx = fe.Context(backend=NumpyBackend())
+    a = ctx.create_array((7, 9))
+    b = ctx.create_array((7, 9))
+    b[1:-1, 1:-1] = 0.3 * (a[:-2, 1:-1] + a[2:, 1:-1] + a[1:-1, :-2] + a[1:-1, 2:])
+    assert fe.match_jacobi(ctx.nodes[-1])[1] == 0.3
+    b[1:-1, 1:-1] = 0.3 * (a[2:, 1:-1] + a[:-2, 1:-1] + a[1:-1, :-2] + a[1:-1, 2:])  # S before N
+    assert fe.match_jacobi(ctx.nodes[-1]) is None
+    b[2:-2, 2:-2] = 1.0 * a[2:-2, 2:-2] + 0.5 * a[1:-3, 2:-2] + 0.5 * a[3:-1, 2:-2] + 0.5 * a[2:-2, 1:-3] + \
+        0.5 * a[2:-2, 3:-1] + 0.25 * a[:-4, 2:-2] + 0.25 * a[4:, 2:-2] + 0.25 * a[2:-2, :-4] + 0.25 * a[2:-2, 4:]
+    m = fe.match_star(ctx.nodes[-1])
+    assert m is not None and m[1] == (1.0, [0.5, 0.25], [0.5, 0.25], [0.5, 0.25], [0.5, 0.25])
+
+
+def test_unsupported_strided_view():
+    ctx = fe.Context(backend=NumpyBackend())
+    a = ctx.create_array((8, 8))
+    with pytest.raises(NotImplementedError):
+        a[::2, :]

@@ -45,16 +45,29 @@ def test_mixed_batch_bit_exact(ops, T):
     _check(outs, u0s, T)
 
 
+@pytest.mark.parametrize("reg", [True, False], ids=["reg", "noreg"])
 @pytest.mark.parametrize("cfg", [(256, 32 * 1024, 4), (512, 64 * 1024, 2), (1024, 160 * 1024, 1),
-                                 (64, 8 * 1024, 8), (128, 2048, 2)])
-def test_launch_configurations(ops, cfg):
-    """Each configuration moves a different set of grids between LDS and global sweeps."""
+                                 (64, 8 * 1024, 8), (128, 2048, 2), (1024, 64 * 1024, 1)])
+def test_launch_configurations(ops, cfg, reg):
+    """Each configuration moves a different set of grids between register, LDS and global sweeps."""
     u0s = [normal_grid(*s, seed=10 + k, dtype=np.float32) for k, s in enumerate(MIXED_SHAPES)]
     plan = ops.BatchPlan([to_dev(u) for u in u0s], 5)
+    plan.set_register_mode(reg)
     plan.configure(*cfg)
     info = plan.info()
-    say(f"batch cfg {cfg} -> {info}")
+    say(f"batch cfg {cfg} reg={reg} -> {info}")
     _check(plan.run(), u0s, 5)
+
+
+def test_register_mode_covers_workload(ops):
+    """With 1024-lane workgroups every grid of the batch workload fits the register mode."""
+    u0s = batch_f32(0)[:64]
+    plan = ops.BatchPlan([to_dev(u) for u in u0s], 7)
+    plan.configure(1024, 160 * 1024, 1)
+    info = plan.info()
+    say(f"batch reg coverage {info}")
+    assert info["n_reg"] == len(u0s)
+    _check(plan.run(), u0s, 7)
 
 
 def test_workload_batch_T10(ops):

@@ -1,0 +1,99 @@
+"""The lazy frontend running on libsten kernels, against the CPU oracle (bit-exact)."""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.star import StarCoef, star_apply
+from tests.gpu_util import device, say, to_host
+from workloads import unit_ring_grid
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fe():
+    device()
+    from paper_2512_19851_amd import frontend
+
+    return frontend
+
+
+@pytest.mark.parametrize("shape,T,depth", [((5, 5), 3, 1), ((64, 64), 10, 4), ((300, 517), 25, 64),
+                                           ((1000, 1000), 40, 1000)])
+def test_listing_program(fe, shape, T, depth):
+    """The listing of the Laplace solver (Section III-A), written as in the paper."""
+    ctx = fe.Context(max_depth=depth)
+    H, W = shape
+    u1 = ctx.create_array((H, W))
+    u2 = ctx.create_array((H, W))
+    u1[0, :] = u1[-1, :] = u1[:, 0] = u1[:, -1] = 1
+    u2[0, :] = u2[-1, :] = u2[:, 0] = u2[:, -1] = 1
+    for _ in range(T):
+        u2[1:-1, 1:-1] = 0.25 * (u1[:-2, 1:-1] + u1[2:, 1:-1] + u1[1:-1, :-2] + u1[1:-1, 2:])
+        u1, u2 = u2, u1
+    say(f"frontend listing {shape} T={T} depth={depth}")
+    got = to_host(u1.tensor())
+    assert np.array_equal(got, oracle.jacobi5(unit_ring_grid(H, W), T))
+    assert ctx.distinct_asts() == 2
+
+
+def test_sub_rectangle_sweep(fe):
+    ctx = fe.Context()
+    a = ctx.create_array((40, 50))
+    b = ctx.create_array((40, 50))
+    a[:, :] = 1.0
+    a[10:20, 5:45] = 3.0
+    b[5:30, 7:41] = 0.3 * (a[4:29, 7:41] + a[6:31, 7:41] + a[5:30, 6:40] + a[5:30, 8:42])
+    say("frontend sub-rectangle")
+    got = to_host(b.tensor())
+    ref_a = np.ones((40, 50))
+    ref_a[10:20, 5:45] = 3.0
+    want = np.zeros((40, 50))
+    want[5:30, 7:41] = 0.3 * (ref_a[4:29, 7:41] + ref_a[6:31, 7:41] + ref_a[5:30, 6:40] + ref_a[5:30, 8:42])
+    assert np.array_equal(got, want)
+
+
+def test_fused_star_program(fe):
+    ctx = fe.Context()
+    rng = np.random.default_rng(0)
+    vals = rng.standard_normal((33, 47))
+    a = ctx.create_array((33, 47))
+    # load values through fills of single points would be slow; set rows with fills of constants instead
+    for i in range(33):
+        a[i, :] = float(vals[i, 0])
+    b = ctx.create_array((33, 47))
+    c = ctx.create_array((33, 47))
+    k1 = StarCoef(0.5, [0.25, 0.125], [0.25, -0.5], [1.5, 0.75], [-0.25, 2.0])
+    k2 = StarCoef(-1.0, [0.3, 0.2], [0.1, 0.9], [0.7, 0.6], [0.5, 0.4])
+
+    def star(x, k):
+        e = k.c0 * x[2:-2, 2:-2]
+        for d in (1, 2):
+            e = e + k.cn[d - 1] * x[2 - d:-2 - d, 2:-2]
+            e = e + k.cs[d - 1] * x[2 + d:(-2 + d) or None, 2:-2]
+            e = e + k.cw[d - 1] * x[2:-2, 2 - d:-2 - d]
+            e = e + k.ce[d - 1] * x[2:-2, 2 + d:(-2 + d) or None]
+        return e
+
+    b[2:-2, 2:-2] = star(a, k1)
+    c[2:-2, 2:-2] = star(a, k2)
+    say("frontend fused star")
+    gb, gc = to_host(b.tensor()), to_host(c.tensor())
+    assert ctx.stats["fused_nodes"] == 2
+    ref = np.repeat(vals[:, :1], 47, axis=1)
+    zb = star_apply(ref, k1)
+    zc = star_apply(ref, k2)
+    # outputs start as zeros outside the assigned region
+    wb = np.zeros((33, 47))
+    wb[2:-2, 2:-2] = zb[2:-2, 2:-2]
+    wc = np.zeros((33, 47))
+    wc[2:-2, 2:-2] = zc[2:-2, 2:-2]
+    assert np.array_equal(gb, wb) and np.array_equal(gc, wc)
+
+
+def test_in_place_rejected_on_gpu(fe):
+    ctx = fe.Context()
+    a = ctx.create_array((8, 8))
+    with pytest.raises(fe.InPlaceDependencyError):
+        a[1:-1, 1:-1] = 0.25 * (a[:-2, 1:-1] + a[2:, 1:-1] + a[1:-1, :-2] + a[1:-1, 2:])
