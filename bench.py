@@ -37,6 +37,9 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "hot-path GB/s or FLOP/s and % roofline, plain FP64 vs mixed/batched at stated tol"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_f64_4096_traffic.json")
 SWEEP_SRC = os.path.join(ROOT, "paper_2512_19851_amd", "csrc", "sweep.hip")
+TB_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_tb_f64_4096_traffic.json")
+TB_SRC = os.path.join(ROOT, "paper_2512_19851_amd", "csrc", "temporal.hip")
+TB_LEVELS = 5  # sweeps per launch of the built-in schedule
 
 
 def log(msg: str) -> None:
@@ -54,13 +57,13 @@ def source_sha(path: str) -> str:
     return hashlib.sha256(text).hexdigest()[:16]
 
 
-def load_traffic(launch_bytes: float):
-    """HBM bytes per launch from committed rocprofv3 counters, if they match this source."""
-    if not os.path.exists(TRAFFIC_FILE):
+def load_traffic(path: str, src: str):
+    """HBM bytes per launch from committed rocprofv3 counters, if they match the kernel source."""
+    if not os.path.exists(path):
         return None
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         rec = json.load(f)
-    if rec.get("source_sha") != source_sha(SWEEP_SRC):
+    if rec.get("source_sha") != source_sha(src):
         return None
     return rec.get("bytes_per_launch")
 
@@ -155,7 +158,7 @@ def bench_mixed(ops, n: int, T: int, args, plain_sec_per_step: float) -> dict:
         "workload": f"{n}x{n} FP64 z*10**U(-3,3) seed 0, encode + {T} hi/lo sweeps + decode per step",
         "ms_per_step": round(sec * 1e3, 4),
         "fp64_equivalent_GBps": round(16.0 * interior * T / sec / 1e9, 1),
-        "speedup_vs_plain_fp64": round(plain_sec_per_step / sec, 3),
+        "speedup_vs_plain_fp64_single_sweep": round(plain_sec_per_step / sec, 3),
         "sweep_kernel_us": round(per_sweep * 1e6, 2),
         "sweep_kernel_GBps_at_12B": round(12.0 * interior / per_sweep / 1e9, 1),
         "sweep_kernel_hbm_frac": round(12.0 * interior / per_sweep / 1e9 / HBM_PEAK_GBS, 4),
@@ -264,7 +267,7 @@ def bench_tiled(ops, n: int, T: int, args, plain_sec_per_step: float) -> dict:
         res[f"{pr}x{pc}"] = {
             "ms_per_step": round(sec * 1e3, 4),
             "effective_GBps": round(16.0 * (n - 2) ** 2 * T / sec / 1e9, 1),
-            "overhead_vs_single_grid": round(sec / plain_sec_per_step, 3),
+            "overhead_vs_single_grid_single_sweep": round(sec / plain_sec_per_step, 3),
             "sweep_launches_per_step": st["sweep_launches"] // (reps + 1) if reps else None,
         }
     res["workload"] = (f"{n}x{n} FP64 N(0,1) seed 0, {T} sweeps per step, tiles with depth-1 ghosts; "
@@ -296,7 +299,7 @@ def bench_temporal(ops, n: int, T: int, args, plain_sec_per_step: float) -> dict
         res[f"levels_{levels}"] = {
             "ms_per_step": round(sec * 1e3, 4),
             "effective_GBps_at_16B": round(16.0 * (n - 2) ** 2 * T / sec / 1e9, 1),
-            "speedup_vs_plain": round(plain_sec_per_step / sec, 3),
+            "speedup_vs_single_sweep": round(plain_sec_per_step / sec, 3),
             "us_per_launch": round(sec / launches * 1e6, 2),
             "hbm_GBps_per_launch_at_16B": round(16.0 * (n - 2) ** 2 / (sec / launches) / 1e9, 1),
         }
@@ -398,13 +401,14 @@ def main() -> int:
     ap.add_argument("--sweeps", type=int, default=100, help="sweeps T per step")
     ap.add_argument("--n", type=int, default=4096, help="grid side")
     ap.add_argument("--kernel-reps", type=int, default=100)
-    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of CPU oracle work")
+    ap.add_argument("--cpu-budget", type=float, default=16.0, help="seconds of CPU oracle work")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extensions", action="store_true")
-    ap.add_argument("--mode", choices=["step", "sweep", "copy", "hilo"], default="step",
+    ap.add_argument("--mode", choices=["step", "sweep", "copy", "hilo", "tb"], default="step",
                     help="step: the benchmark; sweep: only --kernel-reps sweep launches; "
                          "copy: only --kernel-reps plain grid copies (counter calibration); "
-                         "hilo: only --kernel-reps hi/lo sweeps on encoded grids")
+                         "hilo: only --kernel-reps hi/lo sweeps on encoded grids; "
+                         "tb: only --kernel-reps temporally blocked launches")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -463,13 +467,15 @@ def main() -> int:
         for _ in range(args.kernel_reps):
             if args.mode == "sweep":
                 ops.sweep(a, b)
+            elif args.mode == "tb":
+                ops.jacobi5_tb(a, TB_LEVELS, levels=TB_LEVELS, out=b)  # one blocked launch
             else:
                 ops.jacobi5(a, 0, out=b)  # T = 0: one plain copy of the grid
             a, b = b, a
         e1.record()
         torch.cuda.synchronize()
         per = e0.elapsed_time(e1) / args.kernel_reps
-        moved = launch_bytes if args.mode == "sweep" else 16.0 * n * n
+        moved = {"sweep": launch_bytes, "tb": TB_LEVELS * launch_bytes}.get(args.mode, 16.0 * n * n)
         print(json.dumps({"mode": args.mode, "launches": args.kernel_reps, "avg_us": round(per * 1e3, 2),
                           "algorithmic_bytes_per_launch": moved,
                           "GBps": round(moved / (per * 1e-3) / 1e9, 1)}), flush=True)
@@ -497,24 +503,64 @@ def main() -> int:
     value = step_bytes / sec_per_step / 1e9
     log(f"[bench] {sec_per_step * 1e3:.3f} ms/step, {value:.1f} GB/s (events: {ev_ms / args.steps:.3f} ms/step)")
 
+    log("[bench] the same step with one sweep per launch (the paper's schedule)")
+    ops.set_schedule(1)
+    ops.jacobi5(u0, T, out=out, work=work)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ops.jacobi5(u0, T, out=out, work=work)
+    torch.cuda.synchronize()
+    single_sec_per_step = (time.perf_counter() - t0) / args.steps
+    ops.set_schedule(0)
+
     log(f"[bench] per-launch kernel timing, {args.kernel_reps} launches")
     a = out.clone()
     b = work
     b.copy_(a)
+    # the step's dominant kernel: the temporally blocked sweep, TB_LEVELS sweeps per launch
+    w2 = torch.empty_like(u0)
+    ops.jacobi5(a, TB_LEVELS * 2, out=b, work=w2)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    ops.jacobi5(a, TB_LEVELS * args.kernel_reps, out=b, work=w2)  # kernel_reps blocked launches + ring copy
+    e1.record(stream)
+    torch.cuda.synchronize()
+    tb_ms = e0.elapsed_time(e1) / args.kernel_reps
+    tb_bytes = TB_LEVELS * launch_bytes
+    tb_achieved = tb_bytes / (tb_ms * 1e-3) / 1e9
+    roofline = {
+        "bound": "hbm",
+        "achieved": round(tb_achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(tb_achieved / HBM_PEAK_GBS, 4),
+        "traffic": load_traffic(TB_TRAFFIC_FILE, TB_SRC),
+        "kernel": f"sweep_tb_kernel<double,2,8,{TB_LEVELS}> ({TB_LEVELS} sweeps of the 4096x4096 FP64 grid per launch)",
+        "algorithmic_bytes_per_launch": tb_bytes,
+        "avg_launch_us": round(tb_ms * 1e3, 2),
+        "step_us_per_sweep": round(sec_per_step / T * 1e6, 2),
+        "note": "algorithmic bytes count 16 B per interior point per sweep; a launch applies "
+                f"{TB_LEVELS} sweeps while reading and writing the grid once, so achieved exceeds the "
+                "HBM peak and traffic (measured HBM bytes per launch) stays near one sweep's bytes",
+    }
+    # the single-sweep kernel (one sweep per launch, the paper's schedule) for reference
     avg_ms = time_kernel_launches(ops, a, b, args.kernel_reps)
     achieved = launch_bytes / (avg_ms * 1e-3) / 1e9
-    traffic = load_traffic(launch_bytes)
-    roofline = {
+    single = {
         "bound": "hbm",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": traffic,
+        "traffic": load_traffic(TRAFFIC_FILE, SWEEP_SRC),
         "kernel": "sweep_kernel<double,2,4> (one sweep of the 4096x4096 FP64 grid)",
         "algorithmic_bytes_per_launch": launch_bytes,
         "avg_launch_us": round(avg_ms * 1e3, 2),
-        "step_us_per_sweep": round(sec_per_step / T * 1e6, 2),
+        "ms_per_step_single_sweep_schedule": round(single_sec_per_step * 1e3, 4),
+        "GBps_single_sweep_schedule": round(step_bytes / single_sec_per_step / 1e9, 1),
     }
 
     rec = {
@@ -534,18 +580,20 @@ def main() -> int:
             "workload": f"plain FP64 five-point Jacobi, {n}x{n} grid N(0,1) seed 0, {T} sweeps per step",
             "grid": [n, n],
             "sweeps_per_step": T,
+            "schedule": f"temporal blocking, {TB_LEVELS} sweeps per launch (bit-identical to one sweep per launch)",
             "bytes_per_point_per_sweep": 16,
             "parallelism": "single GPU",
         },
         "roofline": roofline,
+        "single_sweep_roofline": single,
     }
 
     if not args.no_extensions:
         rec["extensions"] = {
-            "mixed_hilo": bench_mixed(ops, n, T, args, sec_per_step),
+            "mixed_hilo": bench_mixed(ops, n, T, args, single_sec_per_step),
             "batched": bench_batch(ops, T, args),
-            "tiled": bench_tiled(ops, n, T, args, sec_per_step),
-            "temporal_blocking": bench_temporal(ops, n, T, args, sec_per_step),
+            "tiled": bench_tiled(ops, n, T, args, single_sec_per_step),
+            "temporal_blocking": bench_temporal(ops, n, T, args, single_sec_per_step),
             "frontend": bench_frontend(ops, args),
             "adjoint": bench_adjoint(10, args),
         }

@@ -70,7 +70,10 @@ int sten_last_hip_error(void);
  *              interior is non-empty; may be NULL otherwise.
  *   c          coefficient of the sweep (0.25 in the paper).
  * Bit-exact with the sweep evaluated in FP64 in the listing's order (no fused
- * multiply-add, no reassociation). Errors: STEN_ERR_ARG, STEN_ERR_PTR,
+ * multiply-add, no reassociation). Schedule: when the three grids are 16-byte
+ * aligned with an even ld and T >= 2, several sweeps run per launch
+ * (temporal blocking, 5 by default; see sten_tune_schedule), else one sweep
+ * per launch; both give the same bits. Errors: STEN_ERR_ARG, STEN_ERR_PTR,
  * STEN_ERR_ALIAS (any two of u0, out, work overlap), STEN_ERR_HIP.
  */
 sten_status sten_jacobi5_f64(const double* u0, double* out, double* work,
@@ -96,7 +99,7 @@ sten_status sten_sweep_f32(const float* src, float* dst, int64_t H, int64_t W, i
 
 /*
  * Temporal blocking (the same method, a different schedule): each launch
- * applies `levels` (1..4) sweeps to a tile held in registers, so one pass over
+ * applies `levels` (1..6) sweeps to a tile held in registers, so one pass over
  * HBM serves `levels` sweeps. A tile loads its output block grown by `levels`
  * rows and columns on every side and recomputes that halo. Bit-identical to
  * sten_jacobi5_f64 / _f32 (same arithmetic per point and level). Needs 16-byte
@@ -109,11 +112,20 @@ sten_status sten_jacobi5_f64_tb(const double* u0, double* out, double* work, int
 sten_status sten_jacobi5_f32_tb(const float* u0, float* out, float* work, int64_t H, int64_t W, int64_t ld,
                                 int32_t T, float c, int32_t levels, hipStream_t stream);
 
+/* Tuning hook: output rows per temporally blocked tile (4, 8, 12 or 16; 0
+ * restores the built-in 8). Same bits for every value. */
+sten_status sten_tune_tb_rows(int32_t rows);
+
 /* Scalar slice fill (the listing's ring set-up, Section III-A): rows [r0, r1)
  * x columns [c0, c1) of an H x W FP64 grid get `value`. STEN_ERR_ARG when the
  * rectangle leaves the grid. */
 sten_status sten_fill_rect_f64(double* grid, int64_t H, int64_t W, int64_t ld, int64_t r0, int64_t r1,
                                int64_t c0, int64_t c1, double value, hipStream_t stream);
+
+/* Schedule hook for sten_jacobi5_f64 / _f32: sweeps per launch (1: one sweep
+ * per launch, the paper's one kernel per iteration; 2..6: temporal blocking
+ * with that many; 0: built-in, 5). Process-wide. Same bits for every value. */
+sten_status sten_tune_schedule(int32_t levels);
 
 /* Tuning hook: output rows per workgroup tile of the sweep kernels (4, 8 or
  * 16; 0 restores the built-in choice). Process-wide; not thread-safe against

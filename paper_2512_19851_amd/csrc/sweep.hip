@@ -23,6 +23,12 @@
 #include "common.hpp"
 
 namespace sten {
+
+sten_status run_tb_f64(const double* u0, double* out, double* work, int64_t H, int64_t W, int64_t ld, int32_t T,
+                       double c, int32_t levels, hipStream_t stream);
+sten_status run_tb_f32(const float* u0, float* out, float* work, int64_t H, int64_t W, int64_t ld, int32_t T,
+                       float c, int32_t levels, hipStream_t stream);
+
 namespace {
 
 // BEGIN KERNEL SOURCE (the HBM traffic measurement is keyed to this region)
@@ -211,6 +217,19 @@ __global__ void copy_kernel(const T* __restrict__ src, T* __restrict__ dst, int 
 }
 
 int g_rows_override = 0;  // 0: built-in choice; else rows per tile (tuning hook)
+int g_schedule = 0;       // sweeps per launch of the plain calls: 0 built-in (temporal blocking), 1 single
+
+// Sweeps per launch the plain calls use when the grid allows temporal blocking.
+constexpr int kDefaultLevels = 5;
+
+inline sten_status run_tb_any(const double* u0, double* out, double* work, int64_t H, int64_t W, int64_t ld,
+                              int32_t T, double c, int32_t levels, hipStream_t s) {
+    return run_tb_f64(u0, out, work, H, W, ld, T, c, levels, s);
+}
+inline sten_status run_tb_any(const float* u0, float* out, float* work, int64_t H, int64_t W, int64_t ld,
+                              int32_t T, float c, int32_t levels, hipStream_t s) {
+    return run_tb_f32(u0, out, work, H, W, ld, T, c, levels, s);
+}
 
 template <typename T, int V, int ROWS>
 void launch_sweep_rows(const T* in, T* out, int H, int W, int64_t ld, T c, hipStream_t s) {
@@ -236,6 +255,13 @@ sten_status run_jacobi5(const T* u0, T* out, T* work, int64_t H, int64_t W, int6
     sten_status st = check_grid_args(u0, out, work, need_work, H, W, ld, T_, sizeof(T));
     if (st != STEN_OK || H == 0 || W == 0) return st;
     const int h = (int)H, w = (int)W;
+    constexpr int VT = 16 / (int)sizeof(T);
+    const int levels = g_schedule == 0 ? kDefaultLevels : g_schedule;
+    if (interior && levels > 1 && T_ >= 2 &&
+        ((((uintptr_t)u0 | (uintptr_t)out | (uintptr_t)work) % 16) == 0) && ld % VT == 0) {
+        // same bits, fewer passes over HBM: several sweeps per launch
+        return run_tb_any(u0, out, work, H, W, ld, T_, c, std::min<int32_t>(levels, T_), stream);
+    }
     if (!interior || T_ == 0) {
         const int64_t total = H * W;
         const uint32_t blocks = (uint32_t)std::min<int64_t>((total + 255) / 256, 65536);
@@ -335,6 +361,14 @@ sten_status sten_jacobi5_f64(const double* u0, double* out, double* work, int64_
 sten_status sten_jacobi5_f32(const float* u0, float* out, float* work, int64_t H, int64_t W, int64_t ld,
                              int32_t T, float c, hipStream_t stream) {
     return sten::run_jacobi5<float>(u0, out, work, H, W, ld, T, c, stream);
+}
+
+// Schedule hook: sweeps per launch of the plain calls (1: one sweep per
+// launch; 2..6: temporal blocking with that many; 0: built-in).
+sten_status sten_tune_schedule(int32_t levels) {
+    if (levels < 0 || levels > 6) return STEN_ERR_ARG;
+    sten::g_schedule = levels;
+    return STEN_OK;
 }
 
 // Tuning hook: rows per tile of the sweep kernels (4, 8 or 16; 0 restores the

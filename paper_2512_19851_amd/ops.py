@@ -91,6 +91,16 @@ def jacobi5_tb(u0: torch.Tensor, T: int, c: float = 0.25, levels: int = 2, out: 
     return out
 
 
+def set_schedule(levels: int) -> None:
+    """Sweeps per launch of `jacobi5` (1: one per launch; 2..6: temporal blocking; 0: built-in)."""
+    _lib.call("sten_tune_schedule", int(levels))
+
+
+def set_tb_rows(rows: int) -> None:
+    """Tuning hook: output rows per temporally blocked tile (4, 8, 12, 16; 0 = built-in)."""
+    _lib.call("sten_tune_tb_rows", int(rows))
+
+
 def sweep(src: torch.Tensor, dst: torch.Tensor, c: float = 0.25, stream=None) -> torch.Tensor:
     """One sweep: dst's interior from src (dst's ring untouched); returns dst."""
     fn = {torch.float64: "sten_sweep_f64", torch.float32: "sten_sweep_f32"}.get(src.dtype)

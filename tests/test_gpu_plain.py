@@ -16,12 +16,15 @@ SHAPES = [(1, 1), (2, 9), (9, 2), (3, 3), (4, 4), (5, 7), (63, 65), (64, 64), (3
 TS = [0, 1, 2, 3, 10]
 
 
-@pytest.fixture(scope="module")
-def ops():
+@pytest.fixture(scope="module", params=["auto", "single"])
+def ops(request):
+    """Every plain-path test runs under the built-in schedule and one sweep per launch."""
     device()
     from paper_2512_19851_amd import ops
 
-    return ops
+    ops.set_schedule(0 if request.param == "auto" else 1)
+    yield ops
+    ops.set_schedule(0)
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"{s[0]}x{s[1]}")
