@@ -37,9 +37,9 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "hot-path GB/s or FLOP/s and % roofline, plain FP64 vs mixed/batched at stated tol"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_f64_4096_traffic.json")
 SWEEP_SRC = os.path.join(ROOT, "paper_2512_19851_amd", "csrc", "sweep.hip")
-TB_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_tb_f64_4096_traffic.json")
+TB_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_stream_f64_4096_traffic.json")
 TB_SRC = os.path.join(ROOT, "paper_2512_19851_amd", "csrc", "temporal.hip")
-TB_LEVELS = 5  # sweeps per launch of the built-in schedule
+TB_LEVELS = 8  # sweeps per launch of the built-in schedule
 
 
 def log(msg: str) -> None:
@@ -276,33 +276,43 @@ def bench_tiled(ops, n: int, T: int, args, plain_sec_per_step: float) -> dict:
 
 
 def bench_temporal(ops, n: int, T: int, args, plain_sec_per_step: float) -> dict:
-    """The plain FP64 step with temporal blocking: `levels` sweeps per HBM pass, same bits."""
+    """The plain step with temporal blocking: `levels` sweeps per HBM pass, same bits, for both
+    blocked kernels (register tile, streaming) and both precisions."""
     import torch
 
     from workloads import large_f64
 
     log("[bench] temporal blocking")
-    u0 = torch.from_numpy(large_f64(0, n)).to("cuda:0")
-    out = torch.empty_like(u0)
-    work = torch.empty_like(u0)
-    res = {"workload": f"{n}x{n} FP64 N(0,1) seed 0, {T} sweeps per step, bit-identical to the plain step"}
-    for levels in (2, 3, 4):
-        ops.jacobi5_tb(u0, T, levels=levels, out=out, work=work)
-        torch.cuda.synchronize()
-        reps = max(3, args.steps // 2)
-        t0 = time.perf_counter()
-        for _ in range(reps):
+    u64 = torch.from_numpy(large_f64(0, n)).to("cuda:0")
+    res = {"workload": f"{n}x{n} N(0,1) seed 0, {T} sweeps per step, bit-identical to the plain step"}
+    cases = [("block", 1, torch.float64, (2, 4, 6)), ("stream", 2, torch.float64, (2, 4, 6, 8)),
+             ("stream", 2, torch.float32, (4, 8))]
+    for name, variant, dt, levels_list in cases:
+        u0 = u64.to(dt)
+        out = torch.empty_like(u0)
+        work = torch.empty_like(u0)
+        bpp = 2 * u0.element_size()
+        ops.set_tb(variant, 0, 0)
+        for levels in levels_list:
             ops.jacobi5_tb(u0, T, levels=levels, out=out, work=work)
-        torch.cuda.synchronize()
-        sec = (time.perf_counter() - t0) / reps
-        launches = -(-T // levels)
-        res[f"levels_{levels}"] = {
-            "ms_per_step": round(sec * 1e3, 4),
-            "effective_GBps_at_16B": round(16.0 * (n - 2) ** 2 * T / sec / 1e9, 1),
-            "speedup_vs_single_sweep": round(plain_sec_per_step / sec, 3),
-            "us_per_launch": round(sec / launches * 1e6, 2),
-            "hbm_GBps_per_launch_at_16B": round(16.0 * (n - 2) ** 2 / (sec / launches) / 1e9, 1),
-        }
+            torch.cuda.synchronize()
+            reps = max(3, args.steps // 2)
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ops.jacobi5_tb(u0, T, levels=levels, out=out, work=work)
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t0) / reps
+            launches = -(-T // levels)
+            key = f"{name}_{'f64' if dt == torch.float64 else 'f32'}_levels_{levels}"
+            res[key] = {
+                "ms_per_step": round(sec * 1e3, 4),
+                "us_per_sweep": round(sec / T * 1e6, 3),
+                f"effective_GBps_at_{bpp}B": round(bpp * (n - 2) ** 2 * T / sec / 1e9, 1),
+                "us_per_launch": round(sec / launches * 1e6, 2),
+            }
+            if dt == torch.float64:
+                res[key]["speedup_vs_single_sweep"] = round(plain_sec_per_step / sec, 3)
+    ops.set_tb(0, 0, 0)
     return res
 
 
@@ -531,20 +541,24 @@ def main() -> int:
     tb_ms = e0.elapsed_time(e1) / args.kernel_reps
     tb_bytes = TB_LEVELS * launch_bytes
     tb_achieved = tb_bytes / (tb_ms * 1e-3) / 1e9
+    traffic = load_traffic(TB_TRAFFIC_FILE, TB_SRC)
     roofline = {
         "bound": "hbm",
         "achieved": round(tb_achieved, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(tb_achieved / HBM_PEAK_GBS, 4),
-        "traffic": load_traffic(TB_TRAFFIC_FILE, TB_SRC),
-        "kernel": f"sweep_tb_kernel<double,2,8,{TB_LEVELS}> ({TB_LEVELS} sweeps of the 4096x4096 FP64 grid per launch)",
+        "traffic": traffic,
+        "kernel": f"sweep_stream_kernel<double,2,{TB_LEVELS},4> ({TB_LEVELS} sweeps of the 4096x4096 FP64 grid per launch)",
         "algorithmic_bytes_per_launch": tb_bytes,
         "avg_launch_us": round(tb_ms * 1e3, 2),
         "step_us_per_sweep": round(sec_per_step / T * 1e6, 2),
-        "note": "algorithmic bytes count 16 B per interior point per sweep; a launch applies "
-                f"{TB_LEVELS} sweeps while reading and writing the grid once, so achieved exceeds the "
-                "HBM peak and traffic (measured HBM bytes per launch) stays near one sweep's bytes",
+        "hbm_floor_us_per_launch": round(launch_bytes / (HBM_PEAK_GBS * 1e9) * 1e6, 2),
+        "hbm_use_frac": round(traffic / (tb_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
+        "note": "algorithmic bytes count 16 B per interior point per sweep, as for one sweep per launch; a "
+                f"launch applies {TB_LEVELS} sweeps while reading and writing the grid once, so achieved "
+                "exceeds the HBM peak. traffic is the launch's measured HBM bytes (about one grid read plus "
+                "one write); hbm_use_frac = traffic / launch time / peak is the HBM share the launch uses",
     }
     # the single-sweep kernel (one sweep per launch, the paper's schedule) for reference
     avg_ms = time_kernel_launches(ops, a, b, args.kernel_reps)

@@ -72,7 +72,7 @@ int sten_last_hip_error(void);
  * Bit-exact with the sweep evaluated in FP64 in the listing's order (no fused
  * multiply-add, no reassociation). Schedule: when the three grids are 16-byte
  * aligned with an even ld and T >= 2, several sweeps run per launch
- * (temporal blocking, 5 by default; see sten_tune_schedule), else one sweep
+ * (temporal blocking, 8 by default; see sten_tune_schedule), else one sweep
  * per launch; both give the same bits. Errors: STEN_ERR_ARG, STEN_ERR_PTR,
  * STEN_ERR_ALIAS (any two of u0, out, work overlap), STEN_ERR_HIP.
  */
@@ -99,21 +99,37 @@ sten_status sten_sweep_f32(const float* src, float* dst, int64_t H, int64_t W, i
 
 /*
  * Temporal blocking (the same method, a different schedule): each launch
- * applies `levels` (1..6) sweeps to a tile held in registers, so one pass over
- * HBM serves `levels` sweeps. A tile loads its output block grown by `levels`
- * rows and columns on every side and recomputes that halo. Bit-identical to
- * sten_jacobi5_f64 / _f32 (same arithmetic per point and level). Needs 16-byte
- * aligned u0/out/work and ld a multiple of 2 (FP64) or 4 (FP32), an interior
- * and T >= 1; returns STEN_ERR_UNSUPPORTED otherwise (use the single-sweep
- * entry points for those grids). Other errors as for sten_jacobi5_f64.
+ * applies `levels` sweeps while reading and writing the grid once, so one pass
+ * over HBM serves `levels` sweeps. Two kernels (sten_tune_tb picks one):
+ *  - streaming (built-in, levels 1..8): one wave walks down a band of rows
+ *    and keeps, for every level, the last two rows it produced; each row of
+ *    each level is computed once per band, plus the levels*(levels-1) rows a
+ *    band start needs and the column halo of `levels` on each side of a strip;
+ *  - register tile (levels 1..6): a wave holds its output block grown by
+ *    `levels` rows and columns and recomputes that halo.
+ * Bit-identical to sten_jacobi5_f64 / _f32 (same arithmetic per point and
+ * level, Section III-A). Needs 16-byte aligned u0/out/work and ld a multiple
+ * of 2 (FP64) or 4 (FP32), an interior and T >= 1; returns
+ * STEN_ERR_UNSUPPORTED otherwise (use the single-sweep entry points for those
+ * grids). STEN_ERR_ARG for levels outside the chosen kernel's range. Other
+ * errors as for sten_jacobi5_f64.
  */
 sten_status sten_jacobi5_f64_tb(const double* u0, double* out, double* work, int64_t H, int64_t W, int64_t ld,
                                 int32_t T, double c, int32_t levels, hipStream_t stream);
 sten_status sten_jacobi5_f32_tb(const float* u0, float* out, float* work, int64_t H, int64_t W, int64_t ld,
                                 int32_t T, float c, int32_t levels, hipStream_t stream);
 
-/* Tuning hook: output rows per temporally blocked tile (4, 8, 12 or 16; 0
- * restores the built-in 8). Same bits for every value. */
+/* Tuning hook for the temporally blocked kernels. variant: 0 built-in
+ * (streaming), 1 register tile, 2 streaming. band: output rows per streaming
+ * band (1..65536; 0 built-in: the tallest bands, in whole groups, that let
+ * every resident wave slot hold one band). depth: rows the streaming kernel
+ * loads ahead of the row it computes (4 or 7; 0 built-in 4). Process-wide;
+ * same bits for every setting. STEN_ERR_ARG for other values. */
+sten_status sten_tune_tb(int32_t variant, int32_t band, int32_t depth);
+
+/* Tuning hook: output rows per register tile of the temporally blocked
+ * register-tile kernel (4, 8, 12 or 16; 0 restores the built-in 8). Same bits
+ * for every value. */
 sten_status sten_tune_tb_rows(int32_t rows);
 
 /* Scalar slice fill (the listing's ring set-up, Section III-A): rows [r0, r1)
@@ -123,8 +139,8 @@ sten_status sten_fill_rect_f64(double* grid, int64_t H, int64_t W, int64_t ld, i
                                int64_t c0, int64_t c1, double value, hipStream_t stream);
 
 /* Schedule hook for sten_jacobi5_f64 / _f32: sweeps per launch (1: one sweep
- * per launch, the paper's one kernel per iteration; 2..6: temporal blocking
- * with that many; 0: built-in, 5). Process-wide. Same bits for every value. */
+ * per launch, the paper's one kernel per iteration; 2..8: temporal blocking
+ * with that many; 0: built-in, 8). Process-wide. Same bits for every value. */
 sten_status sten_tune_schedule(int32_t levels);
 
 /* Tuning hook: output rows per workgroup tile of the sweep kernels (4, 8 or

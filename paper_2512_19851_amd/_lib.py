@@ -63,6 +63,7 @@ SIGNATURES = {
     "sten_jacobi5_f64_tb": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, _i64, _i32, _f64, _i32, _vp]),
     "sten_jacobi5_f32_tb": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, _i64, _i32, _f32, _i32, _vp]),
     "sten_tune_tb_rows": (ctypes.c_int, [_i32]),
+    "sten_tune_tb": (ctypes.c_int, [_i32, _i32, _i32]),
     "sten_tune_schedule": (ctypes.c_int, [_i32]),
     "sten_hilo_bytes": (_sz, [_i64, _i64]),
     "sten_jacobi5_f64_hilo_work_bytes": (_sz, [_i64, _i64]),

@@ -737,7 +737,7 @@ sten_status sten_jacobi5_f64_hilo(const double* u0, double* out, void* work, siz
     return check_launch();
 }
 
-// Tuning hook: kernel variant of the hi/lo sweep (1..6; 0 = built-in).
+// Tuning hook: kernel variant of the hi/lo sweep (1..10; 0 = built-in).
 sten_status sten_tune_hilo_variant(int32_t variant) {
     if (variant < 0 || variant > 10) return STEN_ERR_ARG;
     sten::g_hilo_variant = variant;

@@ -220,7 +220,7 @@ int g_rows_override = 0;  // 0: built-in choice; else rows per tile (tuning hook
 int g_schedule = 0;       // sweeps per launch of the plain calls: 0 built-in (temporal blocking), 1 single
 
 // Sweeps per launch the plain calls use when the grid allows temporal blocking.
-constexpr int kDefaultLevels = 5;
+constexpr int kDefaultLevels = 8;
 
 inline sten_status run_tb_any(const double* u0, double* out, double* work, int64_t H, int64_t W, int64_t ld,
                               int32_t T, double c, int32_t levels, hipStream_t s) {
@@ -364,9 +364,9 @@ sten_status sten_jacobi5_f32(const float* u0, float* out, float* work, int64_t H
 }
 
 // Schedule hook: sweeps per launch of the plain calls (1: one sweep per
-// launch; 2..6: temporal blocking with that many; 0: built-in).
+// launch; 2..8: temporal blocking with that many; 0: built-in).
 sten_status sten_tune_schedule(int32_t levels) {
-    if (levels < 0 || levels > 6) return STEN_ERR_ARG;
+    if (levels < 0 || levels > 8) return STEN_ERR_ARG;
     sten::g_schedule = levels;
     return STEN_OK;
 }

@@ -130,6 +130,280 @@ __global__ __launch_bounds__(64) void sweep_tb_kernel(const T* __restrict__ in, 
     }
 }
 
+// Streaming form of the same blocking. One wave owns a strip of 64*V - 2*HALO
+// output columns and a band of output rows [rb, re), and walks along the band
+// once: it loads one row per step (level 0) and, for s = 1..TL, computes level
+// s of the row s behind the loaded one from the last two level-(s-1) rows it
+// keeps and the level-(s-1) row just produced. Level TL of the row TL behind
+// is stored. Unlike the register tile above, no row is computed twice except
+// the TL*(TL-1) rows a band start needs; horizontal neighbours come from DPP
+// lane shifts (no LDS); interior strips skip every column test, and row tests
+// run only where a level's row can leave the interior.
+//
+// Even bands walk down, odd bands walk up, so the 2*TL rows two neighbouring
+// bands both load are loaded by both near the end (or both near the start) of
+// their walks, while they are still in L2. Direction does not change a bit:
+// the sum starts with N + S, and IEEE addition is commutative.
+//
+// Rows that a level computes before its inputs are complete (the first 2s
+// steps of level s) are never read by a stored value: level s+1 first reads
+// level s at step 2s+2, by which time the two rows it keeps were produced at
+// steps 2s and 2s+1, the first steps where level s is complete. The prologue
+// skips those levels outright. Rows outside the grid are loaded clamped to the
+// grid: their values never reach an interior point (an interior row r reads
+// rows r-1 and r+1 only, both inside the grid), so no branch is needed.
+
+// Lane l receives lane l-1's value; lane 0 receives 0 (DPP wave shift right by
+// 1, bound control set, so no register has to be cleared first).
+__device__ __forceinline__ int lane_from_lower_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xF, 0xF, true); }
+// Lane l receives lane l+1's value; lane 63 receives 0 (DPP wave shift left by 1).
+__device__ __forceinline__ int lane_from_upper_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xF, 0xF, true); }
+
+__device__ __forceinline__ float lane_from_lower(float v) {
+    return __builtin_bit_cast(float, lane_from_lower_i(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ float lane_from_upper(float v) {
+    return __builtin_bit_cast(float, lane_from_upper_i(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double lane_from_lower(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)lane_from_lower_i((int)(uint32_t)b);
+    const uint32_t hi = (uint32_t)lane_from_lower_i((int)(uint32_t)(b >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double lane_from_upper(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)lane_from_upper_i((int)(uint32_t)b);
+    const uint32_t hi = (uint32_t)lane_from_upper_i((int)(uint32_t)(b >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Row r (clamped into the grid) of the input into x: V consecutive columns
+// from j0. Edge strips load column by column with the column clamped into the
+// grid as well: a column outside the grid never reaches an interior point (an
+// interior column reads only its two neighbours, both inside the grid), so
+// its value is irrelevant and no lane needs a branch.
+template <typename T, int V, bool COLCHK>
+__device__ __forceinline__ void stream_load(const T* __restrict__ in, int r, int H, int W, int64_t ld, int j0,
+                                            T (&x)[V]) {
+    typedef typename TVec<T, V>::type VT;
+    r = min(max(r, 0), H - 1);
+    const T* row = in + (int64_t)r * ld;
+    if (!COLCHK) {
+        const VT v = *reinterpret_cast<const VT*>(row + j0);
+#pragma unroll
+        for (int e = 0; e < V; ++e) x[e] = v[e];
+    } else {
+#pragma unroll
+        for (int e = 0; e < V; ++e) x[e] = row[min(max(j0 + e, 0), W - 1)];
+    }
+}
+
+// One level of one row: res = c * (((N + S) + W) + E) where the row is
+// interior, else the centre value (boundary ring and outside points keep it).
+// `a` and `b` are the two vertical neighbours (N and S in either order).
+template <typename T, int V, bool COLCHK>
+__device__ __forceinline__ void stream_level(const T (&a)[V], const T (&m)[V], const T (&b)[V], T (&res)[V], T c,
+                                             bool row_in, const bool (&col_in)[V]) {
+    if (!row_in) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) res[e] = m[e];
+        return;
+    }
+    const T lft = lane_from_lower(m[V - 1]);  // column j0 - 1
+    const T rgt = lane_from_upper(m[0]);      // column j0 + V
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+        const T west = (e == 0) ? lft : m[e > 0 ? e - 1 : 0];
+        const T east = (e == V - 1) ? rgt : m[e < V - 1 ? e + 1 : 0];
+        T sum = a[e] + b[e];
+        sum = sum + west;
+        sum = sum + east;
+        const T v = c * sum;
+        res[e] = (!COLCHK || col_in[e]) ? v : m[e];
+    }
+}
+
+// One step: the level-0 row L (x) enters; levels 1..NACT advance by one row
+// each (level s produces row L - dir*s). Level 1 reads the input rows of the
+// last three steps (a0, b0, x: oldest first) straight from the load ring;
+// w0[k], w1[k] hold the two latest rows of level k >= 1, older first. With
+// NACT == TL the level-TL row goes to `top`.
+template <typename T, int V, int TL, int NACT, bool COLCHK, bool ROWCHK>
+__device__ __forceinline__ void stream_step(T (&w0)[TL][V], T (&w1)[TL][V], const T (&a0)[V], const T (&b0)[V],
+                                            const T (&x)[V], T (&top)[V], int L, int dir, int H, T c,
+                                            const bool (&col_in)[V]) {
+    if constexpr (NACT >= 1) {
+        T cur[V];
+        stream_level<T, V, COLCHK>(a0, b0, x, cur, c, !ROWCHK || (L - dir >= 1 && L - dir <= H - 2), col_in);
+#pragma unroll
+        for (int s = 2; s <= NACT; ++s) {
+            const int r = L - dir * s;
+            const bool row_in = !ROWCHK || (r >= 1 && r <= H - 2);
+            T nv[V];
+            stream_level<T, V, COLCHK>(w0[s - 1], w1[s - 1], cur, nv, c, row_in, col_in);
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                w0[s - 1][e] = w1[s - 1][e];
+                w1[s - 1][e] = cur[e];
+                cur[e] = nv[e];
+            }
+        }
+        if constexpr (NACT < TL) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                w0[NACT][e] = w1[NACT][e];
+                w1[NACT][e] = cur[e];
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e) top[e] = cur[e];
+        }
+    }
+}
+
+// Store one finished row (level TL) through a buffer resource that spans
+// just that row: lanes that store nothing get an offset past the row's end,
+// which the hardware drops, and a step past the band (live == false) gets an
+// empty range. No lane branches, so the compiler can count every store in
+// flight and never waits for a younger load than the one a step reads.
+// Interior strips store whole vectors; edge strips store column by column.
+constexpr uint32_t kDropOffset = 0x80000000u;  // past the end of any row range
+constexpr int kRawBufferConfig = 0x00020000;    // raw (untyped) buffer words, gfx9 family
+
+template <typename T, int V, bool COLCHK>
+__device__ __forceinline__ void stream_store(T* __restrict__ out, int r, int64_t ld, int W, bool live,
+                                             uint32_t voff_vec, const uint32_t (&voff_el)[V], const T (&top)[V]) {
+    T* row = out + (int64_t)(live ? r : 1) * ld;  // a dead step's row may lie outside the grid
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(row, 0, live ? W * (int)sizeof(T) : 0, kRawBufferConfig);
+    if constexpr (!COLCHK) {
+        typedef int IV __attribute__((ext_vector_type(4)));
+        static_assert(sizeof(T) * V == sizeof(IV), "one 16-byte vector per lane");
+        typedef typename TVec<T, V>::type VT;
+        VT v;
+#pragma unroll
+        for (int e = 0; e < V; ++e) v[e] = top[e];
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(IV, v), rs, (int)voff_vec, 0, 0);
+    } else {
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            if constexpr (sizeof(T) == 8) {
+                typedef int IV2 __attribute__((ext_vector_type(2)));
+                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(IV2, top[e]), rs, (int)voff_el[e], 0, 0);
+            } else {
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, top[e]), rs, (int)voff_el[e], 0, 0);
+            }
+        }
+    }
+}
+
+// Load ring: P = A + 2 slots; step t reads its row from slot t % P and, once
+// done, loads the row of step t + A into slot (t + A) % P, which held the row
+// of step t - 2, last read by this very step. A loaded row is therefore waited
+// for A steps after its load was issued.
+template <int A>
+struct Ring {
+    static constexpr int P = A + 2;
+    static constexpr int U = (P % 3 == 0) ? P : 3 * P;  // steps per group: whole periods of every rotation
+};
+
+// Steps 0 .. 2*TL-1: level s is complete from step 2s on.
+template <typename T, int V, int TL, int A, int K, bool COLCHK>
+__device__ __forceinline__ void stream_prologue(T (&w0)[TL][V], T (&w1)[TL][V], T (&ring)[Ring<A>::P][V],
+                                                const T* __restrict__ in, int L0, int dir, int H, int W, int64_t ld,
+                                                int j0, T c, const bool (&col_in)[V]) {
+    constexpr int P = Ring<A>::P;
+    if constexpr (K < 2 * TL) {
+        T unused[V];
+        stream_step<T, V, TL, K / 2, COLCHK, true>(w0, w1, ring[(K + P - 2) % P], ring[(K + P - 1) % P], ring[K % P],
+                                                   unused, L0 + dir * K, dir, H, c, col_in);
+        stream_load<T, V, COLCHK>(in, L0 + dir * (K + A), H, W, ld, j0, ring[(K + A) % P]);
+        __builtin_amdgcn_sched_barrier(0);
+        stream_prologue<T, V, TL, A, K + 1, COLCHK>(w0, w1, ring, in, L0, dir, H, W, ld, j0, c, col_in);
+    }
+}
+
+// Every register rotation has a period dividing U: the ring (P) and each
+// level's two kept rows plus its new row (3). An unrolled group of U steps
+// therefore ends with every row back in the register it started in: no
+// copies, and no wait on a load other than the one a step reads.
+template <typename T, int V, int TL, int A, bool COLCHK>
+__device__ __forceinline__ void stream_band(const T* __restrict__ in, T* __restrict__ out, int H, int W, int64_t ld,
+                                            T c, int cs, int rb, int re, int dir) {
+    constexpr int P = Ring<A>::P;
+    constexpr int U = Ring<A>::U;
+    constexpr int HALO = (TL + V - 1) / V * V;
+    constexpr int OW = 64 * V - 2 * HALO;
+    const int lane = threadIdx.x;
+    const int j0 = cs + lane * V;
+    bool col_in[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) col_in[e] = (j0 + e >= 1) && (j0 + e <= W - 2);
+    // store offsets (bytes within the row): the lane's output columns, else dropped
+    const int oc0 = cs + HALO;
+    const bool st_lane = (j0 >= oc0) && (j0 + V <= oc0 + OW);
+    const uint32_t voff_vec = st_lane ? (uint32_t)j0 * (uint32_t)sizeof(T) : kDropOffset;
+    uint32_t voff_el[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) voff_el[e] = (st_lane && col_in[e]) ? (uint32_t)(j0 + e) * (uint32_t)sizeof(T) : kDropOffset;
+
+    // step t loads row L0 + dir*t; the band's rows [rb, re) are stored
+    const int L0 = dir > 0 ? rb - TL : re - 1 + TL;
+    const int nsteps = (re - rb) + 2 * TL;
+    T w0[TL][V], w1[TL][V];
+    T ring[P][V];
+#pragma unroll
+    for (int i = 0; i < A; ++i) stream_load<T, V, COLCHK>(in, L0 + dir * i, H, W, ld, j0, ring[i]);
+    stream_prologue<T, V, TL, A, 0, COLCHK>(w0, w1, ring, in, L0, dir, H, W, ld, j0, c, col_in);
+
+    // Groups of U steps; level rows of step t are L - dir*s for s = 1..TL and
+    // leave [1, H-2] only where the loaded row is outside the grid. The last
+    // group may run past the band (at most U-1 steps): those steps compute
+    // rows that are not stored (and loads stay clamped to the grid).
+    const int ngroups = (nsteps - 2 * TL + U - 1) / U;
+    for (int k = 0; k < ngroups; ++k) {
+        const int g = 2 * TL + k * U;
+        const int La = L0 + dir * g, Lb = L0 + dir * (g + U - 1);
+        const bool rowchk = min(La, Lb) < 0 || max(La, Lb) > H - 1;
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            const int t = 2 * TL + i;  // step index modulo U (g - 2*TL is a multiple of U)
+            const int L = L0 + dir * (g + i);
+            T top[V];
+            if (!rowchk)
+                stream_step<T, V, TL, TL, COLCHK, false>(w0, w1, ring[(t + P - 2) % P], ring[(t + P - 1) % P],
+                                                         ring[t % P], top, L, dir, H, c, col_in);
+            else
+                stream_step<T, V, TL, TL, COLCHK, true>(w0, w1, ring[(t + P - 2) % P], ring[(t + P - 1) % P],
+                                                        ring[t % P], top, L, dir, H, c, col_in);
+            stream_load<T, V, COLCHK>(in, L + dir * A, H, W, ld, j0, ring[(t + A) % P]);
+            stream_store<T, V, COLCHK>(out, L - dir * TL, ld, W, g + i < nsteps, voff_vec, voff_el, top);
+            // keep steps apart: interleaving them only hoists lane shifts and
+            // loads, which costs registers (occupancy) and gains nothing
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+template <typename T, int V, int TL, int A>
+__global__ __launch_bounds__(64) void sweep_stream_kernel(const T* __restrict__ in, T* __restrict__ out, int H, int W,
+                                                         int64_t ld, T c, uint32_t strips, int band) {
+    constexpr int HALO = (TL + V - 1) / V * V;
+    constexpr int OW = 64 * V - 2 * HALO;
+    const uint32_t tile = xcd_tile_of_block(blockIdx.x, gridDim.x);
+    const uint32_t bi = tile / strips;
+    const uint32_t strip = tile - bi * strips;
+    const int cs = (int)strip * OW - HALO;  // first loaded column, a multiple of V
+    const int rb = 1 + (int)bi * band;
+    const int re = min(rb + band, H - 1);
+    const int dir = (bi & 1) ? -1 : 1;
+    if (cs >= 1 && cs + 64 * V <= W - 1)
+        stream_band<T, V, TL, A, false>(in, out, H, W, ld, c, cs, rb, re, dir);
+    else
+        stream_band<T, V, TL, A, true>(in, out, H, W, ld, c, cs, rb, re, dir);
+}
+
 // END KERNEL SOURCE
 
 template <typename T>
@@ -164,7 +438,14 @@ void launch_tb(const T* in, T* out, int H, int W, int64_t ld, T c, hipStream_t s
     sweep_tb_kernel<T, V, ROWS, TL><<<strips * bands, 64, 0, s>>>(in, out, H, W, ld, c, strips);
 }
 
-int g_tb_rows = 0;  // tuning hook: output rows per tile (0: 8)
+int g_tb_rows = 0;     // tuning hook: output rows per register tile (0: 8)
+int g_tb_variant = 0;  // 0: built-in (streaming), 1: register tile, 2: streaming
+int g_tb_band = 0;     // streaming: output rows per band (0: built-in)
+int g_tb_depth = 0;    // streaming: rows loaded ahead (0: built-in 4; 4 or 7)
+
+constexpr int kStreamDepth = 4;
+constexpr int kMaxBlockLevels = 6;
+constexpr int kMaxStreamLevels = 8;
 
 template <typename T, int V, int ROWS>
 void launch_levels_rows(const T* in, T* out, int H, int W, int64_t ld, T c, int levels, hipStream_t s) {
@@ -178,9 +459,9 @@ void launch_levels_rows(const T* in, T* out, int H, int W, int64_t ld, T c, int 
     }
 }
 
-// One blocked launch of `levels` sweeps (1..6).
+// One register-tile launch of `levels` sweeps (1..6).
 template <typename T, int V>
-void launch_levels(const T* in, T* out, int H, int W, int64_t ld, T c, int levels, hipStream_t s) {
+void launch_levels_block(const T* in, T* out, int H, int W, int64_t ld, T c, int levels, hipStream_t s) {
     switch (g_tb_rows) {
         case 4: launch_levels_rows<T, V, 4>(in, out, H, W, ld, c, levels, s); break;
         case 12: launch_levels_rows<T, V, 12>(in, out, H, W, ld, c, levels, s); break;
@@ -189,10 +470,69 @@ void launch_levels(const T* in, T* out, int H, int W, int64_t ld, T c, int level
     }
 }
 
+// Waves of one kernel that fit on the device at once (one wave per workgroup).
+int resident_waves(const void* kernel) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, 0) != hipSuccess)
+        return 0;
+    return cus * per_cu;
+}
+
+template <typename T, int V, int TL, int D>
+void launch_stream(const T* in, T* out, int H, int W, int64_t ld, T c, hipStream_t s) {
+    constexpr int HALO = (TL + V - 1) / V * V;
+    constexpr int OW = 64 * V - 2 * HALO;
+    const uint32_t strips = ceil_div(W - 1, OW);  // strip k stores columns [k*OW, (k+1)*OW)
+    int band = g_tb_band;
+    if (band <= 0) {
+        // Built-in: the tallest bands that still give every resident wave slot
+        // a band, so the grid runs in one round; at least 2*TL rows, so a band
+        // start (2*TL steps) costs at most as much as the band itself.
+        static const int waves = resident_waves(reinterpret_cast<const void*>(&sweep_stream_kernel<T, V, TL, D>));
+        const int64_t fit = std::max<int64_t>(1, (waves > 0 ? waves : 1024) / (int64_t)strips);
+        band = (int)std::max<int64_t>(2 * TL, (H - 2 + fit - 1) / fit);
+        constexpr int U = Ring<D>::U;
+        band = (band + U - 1) / U * U;  // whole groups: no step past the band except in the last band
+    }
+    const uint32_t bands = ceil_div(H - 2, band);
+    sweep_stream_kernel<T, V, TL, D><<<strips * bands, 64, 0, s>>>(in, out, H, W, ld, c, strips, band);
+}
+
+template <typename T, int V, int D>
+void launch_stream_depth(const T* in, T* out, int H, int W, int64_t ld, T c, int levels, hipStream_t s) {
+    switch (levels) {
+        case 1: launch_stream<T, V, 1, D>(in, out, H, W, ld, c, s); break;
+        case 2: launch_stream<T, V, 2, D>(in, out, H, W, ld, c, s); break;
+        case 3: launch_stream<T, V, 3, D>(in, out, H, W, ld, c, s); break;
+        case 4: launch_stream<T, V, 4, D>(in, out, H, W, ld, c, s); break;
+        case 5: launch_stream<T, V, 5, D>(in, out, H, W, ld, c, s); break;
+        case 6: launch_stream<T, V, 6, D>(in, out, H, W, ld, c, s); break;
+        case 7: launch_stream<T, V, 7, D>(in, out, H, W, ld, c, s); break;
+        default: launch_stream<T, V, 8, D>(in, out, H, W, ld, c, s); break;
+    }
+}
+
+// One blocked launch of `levels` sweeps.
+template <typename T, int V>
+void launch_levels(const T* in, T* out, int H, int W, int64_t ld, T c, int levels, hipStream_t s) {
+    // the streaming kernel addresses a row with 32-bit byte offsets
+    const bool stream_fits = (int64_t)W * (int64_t)sizeof(T) < ((int64_t)1 << 30);
+    if (g_tb_variant == 1 || (!stream_fits && levels <= kMaxBlockLevels))
+        return launch_levels_block<T, V>(in, out, H, W, ld, c, levels, s);
+    switch (g_tb_depth > 0 ? g_tb_depth : kStreamDepth) {
+        case 7: launch_stream_depth<T, V, 7>(in, out, H, W, ld, c, levels, s); break;
+        default: launch_stream_depth<T, V, 4>(in, out, H, W, ld, c, levels, s); break;
+    }
+}
+
 template <typename T>
 sten_status run_tb(const T* u0, T* out, T* work, int64_t H, int64_t W, int64_t ld, int32_t T_, T c, int32_t tl,
                    hipStream_t stream) {
-    if (tl < 1 || tl > 6) return STEN_ERR_ARG;
+    if (tl < 1 || tl > (g_tb_variant == 1 ? kMaxBlockLevels : kMaxStreamLevels)) return STEN_ERR_ARG;
+    // rows too wide for the streaming kernel's 32-bit offsets take the register tile
+    if (W * (int64_t)sizeof(T) >= ((int64_t)1 << 30)) tl = std::min(tl, kMaxBlockLevels);
     const bool interior = H >= 3 && W >= 3;
     const int launches = (T_ + tl - 1) / tl;
     const bool need_work = interior && launches >= 2;
@@ -242,6 +582,15 @@ sten_status sten_jacobi5_f64_tb(const double* u0, double* out, double* work, int
 sten_status sten_jacobi5_f32_tb(const float* u0, float* out, float* work, int64_t H, int64_t W, int64_t ld,
                                 int32_t T, float c, int32_t levels, hipStream_t stream) {
     return sten::run_tb<float>(u0, out, work, H, W, ld, T, c, levels, stream);
+}
+
+sten_status sten_tune_tb(int32_t variant, int32_t band, int32_t depth) {
+    if (variant < 0 || variant > 2 || band < 0 || band > 65536) return STEN_ERR_ARG;
+    if (depth != 0 && depth != 4 && depth != 7) return STEN_ERR_ARG;
+    sten::g_tb_variant = variant;
+    sten::g_tb_band = band;
+    sten::g_tb_depth = depth;
+    return STEN_OK;
 }
 
 sten_status sten_tune_tb_rows(int32_t rows) {

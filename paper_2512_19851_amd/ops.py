@@ -92,8 +92,17 @@ def jacobi5_tb(u0: torch.Tensor, T: int, c: float = 0.25, levels: int = 2, out: 
 
 
 def set_schedule(levels: int) -> None:
-    """Sweeps per launch of `jacobi5` (1: one per launch; 2..6: temporal blocking; 0: built-in)."""
+    """Sweeps per launch of `jacobi5` (1: one per launch; 2..8: temporal blocking; 0: built-in)."""
     _lib.call("sten_tune_schedule", int(levels))
+
+
+def set_tb(variant: int = 0, band: int = 0, depth: int = 0) -> None:
+    """Tuning hook for the temporally blocked kernels (0 everywhere restores the built-in choice).
+
+    variant: 1 = register tile (levels 1..6), 2 = streaming (levels 1..8);
+    band: output rows per streaming band; depth: rows the streaming kernel loads ahead (4 or 7).
+    """
+    _lib.call("sten_tune_tb", int(variant), int(band), int(depth))
 
 
 def set_tb_rows(rows: int) -> None:
@@ -205,7 +214,7 @@ def hilo_work_bytes(H: int, W: int, ld: int | None = None) -> int:
 
 
 def set_hilo_variant(variant: int) -> None:
-    """Tuning hook: kernel variant of the hi/lo sweep (1..6, see sten.h; 0 = built-in)."""
+    """Tuning hook: kernel variant of the hi/lo sweep (1..10, see sten.h; 0 = built-in)."""
     _lib.call("sten_tune_hilo_variant", int(variant))
 
 

@@ -73,6 +73,22 @@ def test_tune_hook_rejects_bad_rows(lib):
     assert lib.sten_tune_sweep_rows(0) == 0
 
 
+def test_tune_hooks_validate_and_restore(lib):
+    """Host-only hooks: bad values are rejected, 0 restores the built-in choice."""
+    assert lib.sten_tune_tb(3, 0, 0) == -1          # no such variant
+    assert lib.sten_tune_tb(-1, 0, 0) == -1
+    assert lib.sten_tune_tb(2, -1, 0) == -1         # negative band
+    assert lib.sten_tune_tb(2, 0, 3) == -1          # depth not 4 or 7
+    assert lib.sten_tune_tb(2, 17, 7) == 0
+    assert lib.sten_tune_tb(0, 0, 0) == 0
+    assert lib.sten_tune_schedule(9) == -1
+    assert lib.sten_tune_schedule(-1) == -1
+    assert lib.sten_tune_schedule(8) == 0
+    assert lib.sten_tune_schedule(0) == 0
+    assert lib.sten_tune_tb_rows(5) == -1
+    assert lib.sten_tune_tb_rows(0) == 0
+
+
 def test_validation_before_any_hip_call(lib):
     """Argument errors are reported without touching the GPU (no device here)."""
     f = lib.sten_jacobi5_f64

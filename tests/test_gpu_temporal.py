@@ -1,4 +1,8 @@
-"""Temporal blocking (several sweeps per HBM pass) is bit-identical to the oracle, via the C ABI."""
+"""Temporal blocking (several sweeps per HBM pass) is bit-identical to the oracle, via the C ABI.
+
+Both blocked kernels run: the register tile (levels 1..6) and the streaming
+kernel (levels 1..8, several band heights and load-ahead depths).
+"""
 
 import numpy as np
 import pytest
@@ -9,16 +13,21 @@ from workloads import large_f64, normal_grid
 
 pytestmark = pytest.mark.gpu
 
+BLOCK, STREAM = 1, 2
+VARIANTS = [("block", BLOCK, range(1, 7)), ("stream", STREAM, range(1, 9))]
+
 
 @pytest.fixture(scope="module")
 def ops():
     device()
     from paper_2512_19851_amd import ops
 
-    return ops
+    yield ops
+    ops.set_tb(0, 0, 0)
 
 
 SHAPES = [(3, 3), (5, 7), (9, 130), (64, 64), (63, 65), (257, 1031), (130, 2049), (600, 3), (3, 600), (17, 250)]
+TS = (1, 2, 3, 5, 10, 17)
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
@@ -26,33 +35,86 @@ SHAPES = [(3, 3), (5, 7), (9, 130), (64, 64), (63, 65), (257, 1031), (130, 2049)
 def test_tb_bit_exact(ops, shape, dtype):
     u0 = normal_grid(*shape, seed=sum(shape), dtype=dtype)
     d = to_dev(u0)
-    for levels in (1, 2, 3, 4):
-        for T in (1, 2, 3, 5, 10):
-            say(f"tb {dtype.__name__} {shape} levels={levels} T={T}")
-            got = to_host(ops.jacobi5_tb(d, T, levels=levels))
-            assert np.array_equal(got, oracle.jacobi5(u0, T, dtype=dtype)), f"{shape} L={levels} T={T}"
+    want = {T: oracle.jacobi5(u0, T, dtype=dtype) for T in TS}
+    try:
+        for name, variant, levels_range in VARIANTS:
+            ops.set_tb(variant, 0, 0)
+            for levels in levels_range:
+                for T in TS:
+                    say(f"tb {name} {dtype.__name__} {shape} levels={levels} T={T}")
+                    got = to_host(ops.jacobi5_tb(d, T, levels=levels))
+                    assert np.array_equal(got, want[T]), f"{name} {shape} L={levels} T={T}"
+    finally:
+        ops.set_tb(0, 0, 0)
+
+
+@pytest.mark.parametrize("depth", [4, 7])
+@pytest.mark.parametrize("band", [1, 2, 7, 32, 1000])
+def test_tb_stream_band_and_depth(ops, band, depth):
+    """Band heights that leave a ragged last band, a band of one row, and one band for the whole grid."""
+    cases = [((131, 300), np.float64), ((67, 1030), np.float32), ((40, 2049), np.float64)]
+    try:
+        ops.set_tb(STREAM, band, depth)
+        for shape, dtype in cases:
+            u0 = normal_grid(*shape, seed=band + depth + shape[0], dtype=dtype)
+            d = to_dev(u0)
+            for levels in (1, 3, 5, 8):
+                T = 11
+                say(f"tb stream band={band} depth={depth} {shape} {dtype.__name__} levels={levels}")
+                got = to_host(ops.jacobi5_tb(d, T, levels=levels))
+                assert np.array_equal(got, oracle.jacobi5(u0, T, dtype=dtype)), f"{shape} L={levels}"
+    finally:
+        ops.set_tb(0, 0, 0)
 
 
 def test_tb_general_coefficient(ops):
     u0 = normal_grid(70, 300, seed=2)
-    say("tb c=0.3")
-    assert np.array_equal(to_host(ops.jacobi5_tb(to_dev(u0), 7, 0.3, levels=3)), oracle.jacobi5(u0, 7, 0.3))
+    want = oracle.jacobi5(u0, 7, 0.3)
+    try:
+        for name, variant, _ in VARIANTS:
+            ops.set_tb(variant, 0, 0)
+            say(f"tb {name} c=0.3")
+            assert np.array_equal(to_host(ops.jacobi5_tb(to_dev(u0), 7, 0.3, levels=3)), want)
+    finally:
+        ops.set_tb(0, 0, 0)
+
+
+def test_tb_levels_out_of_range(ops):
+    u0 = to_dev(normal_grid(20, 20, seed=1))
+    try:
+        ops.set_tb(BLOCK, 0, 0)
+        with pytest.raises(ops._lib.StenError):
+            ops.jacobi5_tb(u0, 10, levels=7)
+        ops.set_tb(STREAM, 0, 0)
+        with pytest.raises(ops._lib.StenError):
+            ops.jacobi5_tb(u0, 10, levels=9)
+        with pytest.raises(ops._lib.StenError):
+            ops.jacobi5_tb(u0, 10, levels=0)
+    finally:
+        ops.set_tb(0, 0, 0)
 
 
 def test_tb_full_size(ops):
+    """4096 x 4096 FP64, the benchmark's launch configuration among others, against the oracle."""
     u0 = large_f64(0)
     d = to_dev(u0)
     want = oracle.jacobi5(u0, 10)
-    for levels in (2, 4):
-        say(f"tb 4096 levels={levels} T=10")
-        assert np.array_equal(to_host(ops.jacobi5_tb(d, 10, levels=levels)), want)
+    try:
+        for name, variant, levels_list in [("block", BLOCK, (2, 4, 5)), ("stream", STREAM, (2, 5, 8))]:
+            ops.set_tb(variant, 0, 0)
+            for levels in levels_list:
+                say(f"tb {name} 4096 levels={levels} T=10")
+                assert np.array_equal(to_host(ops.jacobi5_tb(d, 10, levels=levels)), want)
+    finally:
+        ops.set_tb(0, 0, 0)
 
 
 def test_tb_full_size_T100_sampled(ops):
+    """The benchmark's step (built-in schedule, T = 100) on sampled points, each from its dependence cone."""
     u0 = large_f64(0)
     T = 100
-    say("tb 4096 T=100 sampled")
-    got = to_host(ops.jacobi5_tb(to_dev(u0), T, levels=4))
+    say("tb 4096 T=100 sampled (built-in)")
+    got = to_host(ops.jacobi5(to_dev(u0), T))
     H, W = u0.shape
     for (i, j) in sample_points(H, W, 32, seed=3):
         r0, r1, c0, c1 = cone_window(H, W, i, j, T)
