@@ -554,11 +554,15 @@ def main() -> int:
         "avg_launch_us": round(tb_ms * 1e3, 2),
         "step_us_per_sweep": round(sec_per_step / T * 1e6, 2),
         "hbm_floor_us_per_launch": round(launch_bytes / (HBM_PEAK_GBS * 1e9) * 1e6, 2),
+        "launch_floor_frac": round(launch_bytes / (HBM_PEAK_GBS * 1e9) / (tb_ms * 1e-3), 4),
         "hbm_use_frac": round(traffic / (tb_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
         "note": "algorithmic bytes count 16 B per interior point per sweep, as for one sweep per launch; a "
                 f"launch applies {TB_LEVELS} sweeps while reading and writing the grid once, so achieved "
                 "exceeds the HBM peak. traffic is the launch's measured HBM bytes (about one grid read plus "
-                "one write); hbm_use_frac = traffic / launch time / peak is the HBM share the launch uses",
+                "one write); hbm_use_frac = traffic / launch time / peak is the HBM share the launch uses; "
+                "launch_floor_frac = (one grid read plus write at peak) / launch time is the launch's "
+                "distance from its own HBM floor (its arithmetic floor, 4 FP64 ops per point per sweep at "
+                "the 39.3 Tops/s add/multiply rate, is lower)",
     }
     # the single-sweep kernel (one sweep per launch, the paper's schedule) for reference
     avg_ms = time_kernel_launches(ops, a, b, args.kernel_reps)
