@@ -213,6 +213,65 @@ sten_status sten_jacobi5_f64_hilo(const double* u0, double* out, void* work, siz
 sten_status sten_tune_hilo_variant(int32_t variant);
 
 /* ------------------------------------------------------------------------ */
+/* Generated kernels for slice expressions (run-time code generation)        */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * The paper's backend generates one GPU kernel per AST, each thread computing
+ * one element of the output slice, and compiles it at run time in every
+ * process (Section III-C, code generation); consecutive assignments with the
+ * same output shape and no dependence between them run as one kernel (node
+ * fusion, Section III-B). These calls do that for FP64 slice expressions:
+ * the library emits HIP source for a fused group, compiles it with hiprtc for
+ * the current device, caches the code object per program and the kernel per
+ * device, and launches one thread per output element.
+ *
+ * Program text: one expression per output, separated by ';', each in postfix
+ * form with blank-separated tokens:
+ *   L<slot>,<di>,<dj>   input slot `slot` at row offset di, column offset dj
+ *                        from the thread's output point
+ *   C<number>            an FP64 constant (strtod syntax; hexadecimal floats
+ *                        such as C0x1p-2 are exact)
+ *   + - * /              binary operators; the left operand is pushed first
+ *   N                    negation        Q   square (x * x)
+ * Each operation rounds once to FP64 in program order (no fused multiply-add),
+ * as NumPy evaluates the same expression element by element.
+ */
+typedef struct {
+    const double* base;        /* element of the input aligned with output point (0, 0) */
+    int64_t ld;                /* row stride in elements */
+    int64_t row_lo, row_hi;    /* valid rows relative to base (inclusive); loads are checked against them */
+    int64_t col_lo, col_hi;    /* valid columns relative to base (inclusive) */
+} sten_expr_in;
+typedef struct {
+    double* base;              /* output point (0, 0) */
+    int64_t ld;                /* row stride in elements (>= cols) */
+} sten_expr_out;
+
+/* Run a program over a rows x cols output region: output o gets expression o
+ * at every point. Up to 16 input slots and 8 outputs. Checks before any
+ * launch: program syntax and slot numbers (STEN_ERR_ARG, message in
+ * sten_expr_log), every load inside its slot's extent (STEN_ERR_ARG), no
+ * output overlapping an input extent or another output (STEN_ERR_ALIAS, the
+ * paper's rule that an assignment may not read what it writes), device
+ * pointers (STEN_ERR_PTR). STEN_ERR_UNSUPPORTED if the run-time compiler
+ * fails (log in sten_expr_log). rows or cols == 0: nothing to do. */
+sten_status sten_expr_run(const char* program, const sten_expr_in* ins, int32_t nin, const sten_expr_out* outs,
+                          int32_t nout, int64_t rows, int64_t cols, hipStream_t stream);
+
+/* Host only (no GPU needed): the HIP source generated for `program`. Writes at
+ * most cap bytes including the terminating NUL into buf; *len gets the full
+ * length. STEN_ERR_ARG for an invalid program. */
+sten_status sten_expr_source(const char* program, int32_t nin, int32_t nout, char* buf, size_t cap, size_t* len);
+
+/* Host only: compile `program` for `arch` (NULL: "gfx950") with hiprtc and
+ * cache the code object. STEN_ERR_UNSUPPORTED if compilation fails. */
+sten_status sten_expr_compile(const char* program, int32_t nin, int32_t nout, const char* arch);
+
+/* The last program or compiler message of the calling thread ("" if none). */
+const char* sten_expr_log(void);
+
+/* ------------------------------------------------------------------------ */
 /* Batched form: many uneven grids in one persistent launch (extension)     */
 /* ------------------------------------------------------------------------ */
 /*

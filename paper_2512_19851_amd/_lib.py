@@ -97,6 +97,10 @@ SIGNATURES = {
     "sten_tiled_destroy": (ctypes.c_int, [_vp]),
     "sten_star_f64": (ctypes.c_int, [_vp, _vp, _vp, _i32, _i64, _i64, _i64, _vp]),
     "sten_star_iterate_f64": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _i64, _i64, _i32, _vp]),
+    "sten_expr_run": (ctypes.c_int, [ctypes.c_char_p, _vp, _i32, _vp, _i32, _i64, _i64, _vp]),
+    "sten_expr_source": (ctypes.c_int, [ctypes.c_char_p, _i32, _i32, _vp, _sz, ctypes.POINTER(_sz)]),
+    "sten_expr_compile": (ctypes.c_int, [ctypes.c_char_p, _i32, _i32, ctypes.c_char_p]),
+    "sten_expr_log": (ctypes.c_char_p, []),
 }
 
 
@@ -105,6 +109,19 @@ class StarCoefC(ctypes.Structure):
 
     _fields_ = [("radius", _i32), ("reserved", _i32), ("c0", _f64), ("cn", _f64 * 4), ("cs", _f64 * 4),
                 ("cw", _f64 * 4), ("ce", _f64 * 4)]
+
+
+class StenExprIn(ctypes.Structure):
+    """Mirror of sten_expr_in in include/sten.h."""
+
+    _fields_ = [("base", _vp), ("ld", _i64), ("row_lo", _i64), ("row_hi", _i64), ("col_lo", _i64),
+                ("col_hi", _i64)]
+
+
+class StenExprOut(ctypes.Structure):
+    """Mirror of sten_expr_out in include/sten.h."""
+
+    _fields_ = [("base", _vp), ("ld", _i64)]
 
 
 class StenInst(ctypes.Structure):

@@ -6,6 +6,8 @@ Every source under csrc/ is compiled for gfx950 and linked into
                          rounding order (one rounding per operation)
   -packed-fp32-ops off   no packed FP32 instructions are generated
   -O3, -std=c++17, -fPIC, position-independent shared library
+The library links hiprtc, which compiles the generated expression kernels at
+run time (expr.hip).
 """
 
 from __future__ import annotations
@@ -70,7 +72,7 @@ def build(verbose: bool = True) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lhiprtc"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

@@ -14,9 +14,9 @@ This is the paper's programming model on top of libsten, for one GPU::
 What it does, following Section III-A/III-B of the paper:
 
 * every assignment to an array slice records the right side as an expression
-  tree (AST) over slices of other arrays, scalars, +, - and *; the tree is
-  parameterised (arrays are placeholders), so iterations that only swap arrays
-  share one AST;
+  tree (AST) over same-shape slices of other arrays, scalars, +, -, *, /,
+  unary minus and ``** 2``; the tree is parameterised (arrays are
+  placeholders), so iterations that only swap arrays share one AST;
 * an assignment whose right side reads the array it writes is rejected
   (``InPlaceDependencyError``), which is why the listing uses two arrays;
 * nodes form a DAG with true, anti and output dependencies tracked per array
@@ -28,12 +28,15 @@ What it does, following Section III-A/III-B of the paper:
 * before execution, consecutive nodes with the same output region and no path
   between them are fused (node fusion).
 
-Backend (no run-time code generation): recognised ASTs map to libsten kernels -
-scalar fills -> ``sten_fill_rect_f64``; the listing's update
-``c*(N + S + W + E)`` on any rectangle -> ``sten_sweep_f64`` on a view; a
-left-to-right sum of ``coef * shifted slice`` terms in the canonical star
-order -> ``sten_star_f64`` (fused nodes that read the same array share one
-launch). Other expressions raise ``NotImplementedError``.
+Backend: recognised ASTs map to hand-written libsten kernels - scalar fills
+-> ``sten_fill_rect_f64``; the listing's update ``c*(N + S + W + E)`` on any
+rectangle -> ``sten_sweep_f64`` on a view; a left-to-right sum of
+``coef * shifted slice`` terms in the canonical star order ->
+``sten_star_f64`` (fused nodes that read the same array share one launch).
+Every other AST, and every fused group of them, becomes a generated kernel
+(``sten_expr_run``: libsten emits HIP source for the group, compiles it at run
+time and launches one thread per output element), as the paper's backend does
+for all ASTs (Section III-C).
 """
 
 from __future__ import annotations
@@ -71,6 +74,24 @@ class Expr:
     def __rmul__(self, o):
         return BinOp("*", _wrap(o), self)
 
+    def __truediv__(self, o):
+        return BinOp("/", self, _wrap(o))
+
+    def __rtruediv__(self, o):
+        return BinOp("/", _wrap(o), self)
+
+    def __neg__(self):
+        return Unary("neg", self)
+
+    def __pos__(self):
+        return self
+
+    def __pow__(self, k):
+        # NumPy computes x ** 2 as x * x (one rounding); other powers are not supported
+        if isinstance(k, (int, float)) and float(k) == 2.0:
+            return Unary("sq", self)
+        raise NotImplementedError("only ** 2 is supported")
+
 
 @dataclass(eq=False)
 class Const(Expr):
@@ -88,6 +109,12 @@ class BinOp(Expr):
     op: str
     a: Expr
     b: Expr
+
+
+@dataclass(eq=False)
+class Unary(Expr):
+    op: str  # "neg" or "sq"
+    a: Expr
 
 
 def _wrap(v):
@@ -118,6 +145,19 @@ def _arrays(e: Expr, acc: list) -> list:
     elif isinstance(e, BinOp):
         _arrays(e.a, acc)
         _arrays(e.b, acc)
+    elif isinstance(e, Unary):
+        _arrays(e.a, acc)
+    return acc
+
+
+def _refs(e: Expr, acc: list) -> list:
+    if isinstance(e, Ref):
+        acc.append(e)
+    elif isinstance(e, BinOp):
+        _refs(e.a, acc)
+        _refs(e.b, acc)
+    elif isinstance(e, Unary):
+        _refs(e.a, acc)
     return acc
 
 
@@ -128,6 +168,8 @@ def _structure(e: Expr, names: dict) -> str:
     if isinstance(e, Ref):
         k = names.setdefault(e.array.uid, f"A{len(names)}")
         return f"{k}[{e.region}]"
+    if isinstance(e, Unary):
+        return f"{e.op}({_structure(e.a, names)})"
     return f"({_structure(e.a, names)}{e.op}{_structure(e.b, names)})"
 
 
@@ -195,6 +237,11 @@ class Context:
 
     # -- recording ----------------------------------------------------------
     def _assign(self, out: Array, region: tuple, expr: Expr) -> None:
+        shape = (region[1] - region[0], region[3] - region[2])
+        for r in _refs(expr, []):
+            if (r.region[1] - r.region[0], r.region[3] - r.region[2]) != shape:
+                raise ValueError(f"slice of shape {shape} assigned from a slice of another shape "
+                                 "(broadcasting is not supported)")
         ins = _arrays(expr, [])
         if any(a is out for a in ins):
             raise InPlaceDependencyError("the right side reads the array being assigned; use a second array")
@@ -325,6 +372,85 @@ def match_star(node: Node):
 
 
 # ---------------------------------------------------------------------------
+# Expression programs for generated kernels
+# ---------------------------------------------------------------------------
+
+EXPR_MAX_IN = 16   # input slots of one generated kernel (libsten limit)
+EXPR_MAX_OUT = 8   # outputs of one generated kernel (libsten limit)
+
+
+def node_kind(node: Node) -> str:
+    """'fill', 'jacobi', 'star' (hand-written kernels) or 'expr' (generated kernel)."""
+    if isinstance(node.expr, Const):
+        return "fill"
+    if match_jacobi(node) is not None and node.ins[0].shape == node.out.shape:
+        return "jacobi"
+    if match_star(node) is not None:
+        return "star"
+    return "expr"
+
+
+def build_program(nodes: list) -> tuple:
+    """One postfix program for a fused group of same-shape nodes (grammar in include/sten.h).
+
+    Returns (text, ins, outs, rows, cols): ins and outs are (array, r0, c0) triples, the element of
+    each array aligned with output point (0, 0). An input slot is one array seen from one output
+    origin; every load is an offset from it. Constants are written as exact hexadecimal floats.
+    """
+    r0, r1, c0, c1 = nodes[0].region
+    rows, cols = r1 - r0, c1 - c0
+    slots: dict = {}
+    ins: list = []
+    outs: list = []
+    texts = []
+    for n in nodes:
+        o0, o1, p0, p1 = n.region
+        if (o1 - o0, p1 - p0) != (rows, cols):
+            raise ValueError("fused nodes must have one output shape")
+        toks: list = []
+
+        def emit(e):
+            if isinstance(e, Const):
+                toks.append("C" + float(e.value).hex())
+            elif isinstance(e, Ref):
+                key = (e.array.uid, o0, p0)
+                if key not in slots:
+                    slots[key] = len(ins)
+                    ins.append((e.array, o0, p0))
+                toks.append(f"L{slots[key]},{e.region[0] - o0},{e.region[2] - p0}")
+            elif isinstance(e, Unary):
+                emit(e.a)
+                toks.append({"neg": "N", "sq": "Q"}[e.op])
+            else:
+                emit(e.a)
+                emit(e.b)
+                toks.append(e.op)
+
+        emit(n.expr)
+        texts.append(" ".join(toks))
+        outs.append((n.out, o0, p0))
+    return "; ".join(texts), ins, outs, rows, cols
+
+
+def split_for_limits(nodes: list) -> list:
+    """Consecutive chunks of a fused group that fit one generated kernel's slot and output limits."""
+    chunks, cur = [], []
+    for n in nodes:
+        trial = cur + [n]
+        _, ins, outs, _, _ = build_program(trial)
+        if cur and (len(ins) > EXPR_MAX_IN or len(outs) > EXPR_MAX_OUT):
+            chunks.append(cur)
+            trial = [n]
+        cur = trial
+    if cur:
+        chunks.append(cur)
+    for c in chunks:
+        if len(build_program(c)[1]) > EXPR_MAX_IN:
+            raise NotImplementedError(f"an expression reads more than {EXPR_MAX_IN} slices of distinct arrays")
+    return chunks
+
+
+# ---------------------------------------------------------------------------
 # GPU backend (libsten)
 # ---------------------------------------------------------------------------
 
@@ -344,41 +470,45 @@ class GpuBackend:
         return self.torch.zeros(shape, dtype=self.torch.float64, device=self.device)
 
     def fusable(self, a: Node, b: Node) -> bool:
-        sa, sb = match_star(a), match_star(b)
-        return sa is not None and sb is not None and sa[0] is sb[0] and len(sa[1][1]) == len(sb[1][1])
+        ka, kb = node_kind(a), node_kind(b)
+        if ka == "star" and kb == "star":
+            sa, sb = match_star(a), match_star(b)
+            return sa[0] is sb[0] and len(sa[1][1]) == len(sb[1][1])
+        return ka == "expr" and kb == "expr"
 
     def run(self, group: list) -> None:
         from . import _lib
         from .ops import _ld, _stream_ptr
 
-        if len(group) > 1:  # fused star stencils reading one array
+        kind = node_kind(group[0])
+        if len(group) > 1 and kind == "star":  # fused star stencils reading one array
             src = match_star(group[0])[0]
             specs = [match_star(n)[1] for n in group]
             self.ops.star(src.data, specs, outs=[n.out.data for n in group])
             return
-        n = group[0]
-        H, W = n.out.shape
-        r0, r1, c0, c1 = n.region
-        if isinstance(n.expr, Const):
-            _lib.call("sten_fill_rect_f64", n.out.data.data_ptr(), H, W, _ld(n.out.data), r0, r1, c0, c1,
-                      float(n.expr.value), _stream_ptr())
-            return
-        m = match_jacobi(n)
-        if m is not None:
-            src, c = m
-            if src.shape != n.out.shape:
-                raise NotImplementedError("sweep between arrays of different shapes")
-            # view of the region grown by one: the sweep writes exactly its interior
-            vs = src.data[r0 - 1:r1 + 1, c0 - 1:c1 + 1]
-            vd = n.out.data[r0 - 1:r1 + 1, c0 - 1:c1 + 1]
-            _lib.call("sten_sweep_f64", vs.data_ptr(), vd.data_ptr(), vs.shape[0], vs.shape[1], _ld(src.data),
-                      float(c), _stream_ptr())
-            return
-        s = match_star(n)
-        if s is not None:
+        if len(group) == 1 and kind != "expr":
+            n = group[0]
+            H, W = n.out.shape
+            r0, r1, c0, c1 = n.region
+            if kind == "fill":
+                _lib.call("sten_fill_rect_f64", n.out.data.data_ptr(), H, W, _ld(n.out.data), r0, r1, c0, c1,
+                          float(n.expr.value), _stream_ptr())
+                return
+            if kind == "jacobi":
+                src, c = match_jacobi(n)
+                # view of the region grown by one: the sweep writes exactly its interior
+                vs = src.data[r0 - 1:r1 + 1, c0 - 1:c1 + 1]
+                vd = n.out.data[r0 - 1:r1 + 1, c0 - 1:c1 + 1]
+                _lib.call("sten_sweep_f64", vs.data_ptr(), vd.data_ptr(), vs.shape[0], vs.shape[1],
+                          _ld(src.data), float(c), _stream_ptr())
+                return
+            s = match_star(n)
             self.ops.star(s[0].data, [s[1]], outs=[n.out.data])
             return
-        raise NotImplementedError(f"expression not supported by the backend: {n.ast}")
+        for chunk in split_for_limits(group):
+            text, ins, outs, rows, cols = build_program(chunk)
+            self.ops.expr_run(text, [(a.data, r0, c0) for a, r0, c0 in ins],
+                              [(a.data, r0, c0) for a, r0, c0 in outs], rows, cols)
 
     def synchronize(self) -> None:
         self.torch.cuda.synchronize()

@@ -421,3 +421,66 @@ def star_iterate(u0: torch.Tensor, T: int, spec, out=None, work=None, stream=Non
     _lib.call("sten_star_iterate_f64", u0.data_ptr(), out.data_ptr(), work.data_ptr() if work is not None else None,
               ctypes.cast(ctypes.pointer(coef), ctypes.c_void_p), H, W, _ld(u0), int(T), _stream_ptr(stream))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Generated kernels for slice expressions
+# ---------------------------------------------------------------------------
+
+def expr_source(program: str, nin: int, nout: int) -> str:
+    """The HIP source libsten generates for an expression program (host only, no GPU)."""
+    import ctypes
+
+    n = ctypes.c_size_t(0)
+    _lib.check("sten_expr_source", _lib.load().sten_expr_source(program.encode(), nin, nout, None, 0,
+                                                                 ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value + 1)
+    _lib.call("sten_expr_source", program.encode(), nin, nout, ctypes.cast(buf, ctypes.c_void_p), n.value + 1,
+              ctypes.byref(n))
+    return buf.value.decode()
+
+
+def expr_compile(program: str, nin: int, nout: int, arch: str = "gfx950") -> None:
+    """Compile an expression program with the run-time compiler (host only, no GPU); raises on failure."""
+    code = _lib.load().sten_expr_compile(program.encode(), nin, nout, arch.encode())
+    if code != 0:
+        raise _lib.StenError("sten_expr_compile", code, None) from RuntimeError(expr_log())
+
+
+def expr_log() -> str:
+    """The last expression-program or compiler message of this thread."""
+    return _lib.load().sten_expr_log().decode()
+
+
+def expr_run(program: str, ins, outs, rows: int, cols: int, stream=None) -> None:
+    """Run an expression program over a rows x cols region.
+
+    ins / outs: lists of (tensor, r0, c0): FP64 grids and the element of each that is aligned with
+    output point (0, 0). Input extents are the whole tensors; libsten checks every load against them.
+    """
+    import ctypes
+
+    ia = (_lib.StenExprIn * max(1, len(ins)))()
+    for k, (t, r0, c0) in enumerate(ins):
+        _check_grid(t, torch.float64, f"input {k}")
+        H, W = t.shape
+        ld = _ld(t)
+        ia[k].base = t.data_ptr() + (r0 * ld + c0) * 8
+        ia[k].ld = ld
+        ia[k].row_lo, ia[k].row_hi = -r0, H - 1 - r0
+        ia[k].col_lo, ia[k].col_hi = -c0, W - 1 - c0
+    oa = (_lib.StenExprOut * max(1, len(outs)))()
+    for k, (t, r0, c0) in enumerate(outs):
+        _check_grid(t, torch.float64, f"output {k}")
+        H, W = t.shape
+        if r0 < 0 or c0 < 0 or r0 + rows > H or c0 + cols > W:
+            raise ValueError(f"output {k}: region leaves the array")
+        ld = _ld(t)
+        oa[k].base = t.data_ptr() + (r0 * ld + c0) * 8
+        oa[k].ld = ld
+    code = _lib.load().sten_expr_run(program.encode(), ctypes.cast(ia, ctypes.c_void_p), len(ins),
+                                     ctypes.cast(oa, ctypes.c_void_p), len(outs), int(rows), int(cols),
+                                     _stream_ptr(stream))
+    if code != 0:
+        raise _lib.StenError("sten_expr_run", code, _lib.load().sten_last_hip_error() if code == -5 else None) \
+            from RuntimeError(expr_log())

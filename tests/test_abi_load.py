@@ -110,3 +110,28 @@ def test_tiled_workspace_query(lib):
     one = lib.sten_tiled_workspace_bytes(100, 100, 1, 1)
     many = lib.sten_tiled_workspace_bytes(100, 100, 4, 4)
     assert many > one  # ghost frames and send buffers grow with the tile count
+
+
+def test_expr_run_rejects_before_any_hip_call(lib):
+    """Program syntax, load extents and aliasing are checked on the host (fake pointers, no device)."""
+    import ctypes
+
+    from paper_2512_19851_amd import _lib
+
+    ins = (_lib.StenExprIn * 1)()
+    ins[0].base, ins[0].ld = 0x10000000, 100
+    ins[0].row_lo, ins[0].row_hi, ins[0].col_lo, ins[0].col_hi = -1, 8, -1, 98
+    outs = (_lib.StenExprOut * 1)()
+    outs[0].base, outs[0].ld = 0x20000000, 100
+    run = lambda prog, rows, cols: lib.sten_expr_run(  # noqa: E731
+        prog, ctypes.cast(ins, ctypes.c_void_p), 1, ctypes.cast(outs, ctypes.c_void_p), 1, rows, cols, None)
+    assert run(b"L0,1,0 L0,-1,0 +", 9, 98) == -1          # last row 8, plus 1, leaves the extent
+    assert run(b"L0,1,0 L0,-1,0 +", 8, 98) == -3          # inside: checks pass, the fake pointer does not
+    assert run(b"L0,0,0 *", 4, 4) == -1                   # bad postfix
+    assert run(b"L1,0,0", 4, 4) == -1                     # no slot 1
+    assert run(b"L0,0,0; L0,0,0", 4, 4) == -1             # two expressions, one output
+    outs[0].base = 0x10000000 + 8 * 50                    # output inside the input's extent
+    assert run(b"L0,0,0", 4, 4) == -2
+    outs[0].base = 0x20000000
+    assert run(b"L0,0,0", 0, 4) == 0                      # empty region
+    assert b"expression" in lib.sten_expr_log() or lib.sten_expr_log() == b""

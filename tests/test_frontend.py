@@ -9,39 +9,7 @@ import numpy as np
 import pytest
 
 from paper_2512_19851_amd import frontend as fe
-
-
-class NumpyBackend:
-    """Executes nodes eagerly in NumPy and records the launch groups."""
-
-    def __init__(self):
-        self.groups = []
-
-    def alloc(self, shape):
-        return np.zeros(shape)
-
-    def fusable(self, a, b):
-        sa, sb = fe.match_star(a), fe.match_star(b)
-        return sa is not None and sb is not None and sa[0] is sb[0] and len(sa[1][1]) == len(sb[1][1])
-
-    def _eval(self, e):
-        if isinstance(e, fe.Const):
-            return e.value
-        if isinstance(e, fe.Ref):
-            r0, r1, c0, c1 = e.region
-            return e.array.data[r0:r1, c0:c1].copy()
-        a, b = self._eval(e.a), self._eval(e.b)
-        return {"+": lambda: a + b, "-": lambda: a - b, "*": lambda: a * b}[e.op]()
-
-    def run(self, group):
-        self.groups.append([(n.ast, fe.match_jacobi(n) is not None, fe.match_star(n) is not None) for n in group])
-        vals = [self._eval(n.expr) for n in group]  # fused nodes read before any writes
-        for n, v in zip(group, vals):
-            r0, r1, c0, c1 = n.region
-            n.out.data[r0:r1, c0:c1] = v
-
-    def synchronize(self):
-        pass
+from tests.numpy_backend import NumpyBackend
 
 
 def listing(ctx, H, W, T):
