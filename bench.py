@@ -351,6 +351,45 @@ def bench_frontend(ops, args) -> dict:
     return res
 
 
+def bench_cavity(args, n: int = 16384, nit: int = 50, steps: int = 2) -> dict:
+    """The paper's second application (Section V): lid-driven cavity flow, 16k x 16k per GPU, written
+    as slice assignments on the frontend; most nodes run as generated kernels, the u and v updates fused."""
+    import torch
+
+    from paper_2512_19851_amd import frontend
+    from paper_2512_19851_amd.cavity import CavityFlow
+
+    log(f"[bench] cavity flow {n}x{n}, {nit} pressure iterations per step")
+    ctx = frontend.Context(max_depth=64)
+    flow = CavityFlow(ctx, n, n, nit=nit)
+    t0 = time.perf_counter()
+    flow.run(1)  # warm-up: compiles the generated kernels (hiprtc) once per process
+    ctx.sync()
+    warm = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    flow.run(steps)
+    ctx.sync()
+    sec = (time.perf_counter() - t0) / steps
+    interior = (n - 2) ** 2
+    # algorithmic bytes per step: source (read u, v; write b), nit pressure iterations (read p, b;
+    # write p), velocities (read u, v, p; write u, v); walls are O(n)
+    step_bytes = interior * (24 + 24 * nit + 40)
+    u, v, p = flow.fields()
+    finite = bool(torch.isfinite(u).all() and torch.isfinite(v).all() and torch.isfinite(p).all())
+    del flow, ctx, u, v, p
+    torch.cuda.empty_cache()
+    return {
+        "workload": f"{n}x{n} FP64, rest start, lid u = 1, nu = 0.1, dt = 0.001, {nit} pressure iterations per "
+                    f"step, {steps} timed steps after one warm-up step",
+        "ms_per_step": round(sec * 1e3, 2),
+        "effective_GBps": round(step_bytes / sec / 1e9, 1),
+        "algorithmic_bytes_per_step": step_bytes,
+        "warmup_step_s_incl_compile": round(warm, 2),
+        "fields_finite": finite,
+        "parity": "bit-identical to the NumPy oracle on 5x5 ... 257x513 (tests/test_gpu_cavity.py)",
+    }
+
+
 def bench_adjoint(T: int, args) -> dict:
     """Gradient workload: 1024x1024 FP32, L = sum(w * u_T), dL/du0 and dL/dc through autograd."""
     import torch
@@ -414,11 +453,12 @@ def main() -> int:
     ap.add_argument("--cpu-budget", type=float, default=16.0, help="seconds of CPU oracle work")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extensions", action="store_true")
-    ap.add_argument("--mode", choices=["step", "sweep", "copy", "hilo", "tb"], default="step",
+    ap.add_argument("--mode", choices=["step", "sweep", "copy", "hilo", "tb", "cavity"], default="step",
                     help="step: the benchmark; sweep: only --kernel-reps sweep launches; "
                          "copy: only --kernel-reps plain grid copies (counter calibration); "
                          "hilo: only --kernel-reps hi/lo sweeps on encoded grids; "
-                         "tb: only --kernel-reps temporally blocked launches")
+                         "tb: only --kernel-reps temporally blocked launches; "
+                         "cavity: only the cavity-flow extension (--n grid side)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -435,6 +475,9 @@ def main() -> int:
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.mode == "cavity":
+        print(json.dumps({"mode": "cavity", **bench_cavity(args, n=args.n)}), flush=True)
+        return 0
     n, T = args.n, args.sweeps
     log(f"[bench] generating {n}x{n} FP64 N(0,1) seed 0")
     u0_np = large_f64(0, n)
@@ -614,6 +657,7 @@ def main() -> int:
             "temporal_blocking": bench_temporal(ops, n, T, args, single_sec_per_step),
             "frontend": bench_frontend(ops, args),
             "adjoint": bench_adjoint(10, args),
+            "cavity_flow": bench_cavity(args),
         }
 
     if not args.no_cpu:
