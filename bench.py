@@ -39,7 +39,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_f64_4096_traffic.json")
 SWEEP_SRC = os.path.join(ROOT, "paper_2512_19851_amd", "csrc", "sweep.hip")
 TB_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_stream_f64_4096_traffic.json")
 TB_SRC = os.path.join(ROOT, "paper_2512_19851_amd", "csrc", "temporal.hip")
-TB_LEVELS = 8  # sweeps per launch of the built-in schedule
+TB_LEVELS = 10  # sweeps per launch of the built-in schedule
+PREWARM_S = 0.25  # seconds of untimed steps before the timed region
 
 
 def log(msg: str) -> None:
@@ -285,8 +286,8 @@ def bench_temporal(ops, n: int, T: int, args, plain_sec_per_step: float) -> dict
     log("[bench] temporal blocking")
     u64 = torch.from_numpy(large_f64(0, n)).to("cuda:0")
     res = {"workload": f"{n}x{n} N(0,1) seed 0, {T} sweeps per step, bit-identical to the plain step"}
-    cases = [("block", 1, torch.float64, (2, 4, 6)), ("stream", 2, torch.float64, (2, 4, 6, 8)),
-             ("stream", 2, torch.float32, (4, 8))]
+    cases = [("block", 1, torch.float64, (2, 4, 6)), ("stream", 2, torch.float64, (2, 4, 6, 8, 10, 12)),
+             ("stream", 2, torch.float32, (4, 8, 10, 12))]
     for name, variant, dt, levels_list in cases:
         u0 = u64.to(dt)
         out = torch.empty_like(u0)
@@ -534,10 +535,16 @@ def main() -> int:
                           "GBps": round(moved / (per * 1e-3) / 1e9, 1)}), flush=True)
         return 0
 
-    log(f"[bench] warmup {args.warmup} steps of T={T}")
+    log(f"[bench] warmup {args.warmup} steps of T={T}, then the same step until {PREWARM_S} s have passed")
     for _ in range(args.warmup):
         ops.jacobi5(u0, T, out=out, work=work)
     torch.cuda.synchronize()
+    # Clocks ramp up over the first tens of milliseconds of sustained work (a cold start ran the first
+    # steps about 15% slower); run the untimed step until the GPU has been busy for PREWARM_S seconds.
+    t_warm = time.perf_counter()
+    while time.perf_counter() - t_warm < PREWARM_S:
+        ops.jacobi5(u0, T, out=out, work=work)
+        torch.cuda.synchronize()
 
     log(f"[bench] timing {args.steps} steps")
     stream = torch.cuda.current_stream()

@@ -72,7 +72,8 @@ int sten_last_hip_error(void);
  * Bit-exact with the sweep evaluated in FP64 in the listing's order (no fused
  * multiply-add, no reassociation). Schedule: when the three grids are 16-byte
  * aligned with an even ld and T >= 2, several sweeps run per launch
- * (temporal blocking, 8 by default; see sten_tune_schedule), else one sweep
+ * (temporal blocking, at most 10 (FP64) or 8 (FP32) by default, T split evenly
+ * over the launches; see sten_tune_schedule), else one sweep
  * per launch; both give the same bits. Errors: STEN_ERR_ARG, STEN_ERR_PTR,
  * STEN_ERR_ALIAS (any two of u0, out, work overlap), STEN_ERR_HIP.
  */
@@ -99,9 +100,10 @@ sten_status sten_sweep_f32(const float* src, float* dst, int64_t H, int64_t W, i
 
 /*
  * Temporal blocking (the same method, a different schedule): each launch
- * applies `levels` sweeps while reading and writing the grid once, so one pass
- * over HBM serves `levels` sweeps. Two kernels (sten_tune_tb picks one):
- *  - streaming (built-in, levels 1..8): one wave walks down a band of rows
+ * applies up to `levels` sweeps while reading and writing the grid once, so one
+ * pass over HBM serves several sweeps (the T sweeps are split as evenly as
+ * ceil(T / levels) launches allow). Two kernels (sten_tune_tb picks one):
+ *  - streaming (built-in, levels 1..12): one wave walks down a band of rows
  *    and keeps, for every level, the last two rows it produced; each row of
  *    each level is computed once per band, plus the levels*(levels-1) rows a
  *    band start needs and the column halo of `levels` on each side of a strip;
@@ -123,8 +125,8 @@ sten_status sten_jacobi5_f32_tb(const float* u0, float* out, float* work, int64_
  * (streaming), 1 register tile, 2 streaming. band: output rows per streaming
  * band (1..65536; 0 built-in: the tallest bands, in whole groups, that let
  * every resident wave slot hold one band). depth: rows the streaming kernel
- * loads ahead of the row it computes (4 or 7; 0 built-in 4). Process-wide;
- * same bits for every setting. STEN_ERR_ARG for other values. */
+ * loads ahead of the row it computes (0 or 4, the one depth built). Process-
+ * wide; same bits for every setting. STEN_ERR_ARG for other values. */
 sten_status sten_tune_tb(int32_t variant, int32_t band, int32_t depth);
 
 /* Tuning hook: output rows per register tile of the temporally blocked
@@ -139,8 +141,9 @@ sten_status sten_fill_rect_f64(double* grid, int64_t H, int64_t W, int64_t ld, i
                                int64_t c0, int64_t c1, double value, hipStream_t stream);
 
 /* Schedule hook for sten_jacobi5_f64 / _f32: sweeps per launch (1: one sweep
- * per launch, the paper's one kernel per iteration; 2..8: temporal blocking
- * with that many; 0: built-in, 8). Process-wide. Same bits for every value. */
+ * per launch, the paper's one kernel per iteration; 2..12: temporal blocking
+ * with at most that many; 0: built-in, 10 for FP64, 8 for FP32). Process-wide.
+ * Same bits for every value. */
 sten_status sten_tune_schedule(int32_t levels);
 
 /* Tuning hook: output rows per workgroup tile of the sweep kernels (4, 8 or

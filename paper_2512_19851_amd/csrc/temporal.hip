@@ -178,18 +178,26 @@ __device__ __forceinline__ double lane_from_upper(double v) {
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// Strip kinds: EDGE 0, a strip whose loaded columns are all interior (no
+// column test at all); EDGE 1, a strip that touches the grid's first or last
+// column but loads only columns inside the grid (the two boundary columns keep
+// their value by a select, and stores are whole vectors: a boundary column is
+// stored with its unchanged input value, which the output already holds);
+// EDGE 2, a strip whose loads may leave the grid (columns clamped, stored
+// column by column).
+
 // Row r (clamped into the grid) of the input into x: V consecutive columns
-// from j0. Edge strips load column by column with the column clamped into the
-// grid as well: a column outside the grid never reaches an interior point (an
-// interior column reads only its two neighbours, both inside the grid), so
+// from j0. EDGE 2 strips load column by column with the column clamped into
+// the grid as well: a column outside the grid never reaches an interior point
+// (an interior column reads only its two neighbours, both inside the grid), so
 // its value is irrelevant and no lane needs a branch.
-template <typename T, int V, bool COLCHK>
+template <typename T, int V, int EDGE>
 __device__ __forceinline__ void stream_load(const T* __restrict__ in, int r, int H, int W, int64_t ld, int j0,
                                             T (&x)[V]) {
     typedef typename TVec<T, V>::type VT;
     r = min(max(r, 0), H - 1);
     const T* row = in + (int64_t)r * ld;
-    if (!COLCHK) {
+    if constexpr (EDGE < 2) {
         const VT v = *reinterpret_cast<const VT*>(row + j0);
 #pragma unroll
         for (int e = 0; e < V; ++e) x[e] = v[e];
@@ -202,7 +210,7 @@ __device__ __forceinline__ void stream_load(const T* __restrict__ in, int r, int
 // One level of one row: res = c * (((N + S) + W) + E) where the row is
 // interior, else the centre value (boundary ring and outside points keep it).
 // `a` and `b` are the two vertical neighbours (N and S in either order).
-template <typename T, int V, bool COLCHK>
+template <typename T, int V, int EDGE>
 __device__ __forceinline__ void stream_level(const T (&a)[V], const T (&m)[V], const T (&b)[V], T (&res)[V], T c,
                                              bool row_in, const bool (&col_in)[V]) {
     if (!row_in) {
@@ -220,7 +228,7 @@ __device__ __forceinline__ void stream_level(const T (&a)[V], const T (&m)[V], c
         sum = sum + west;
         sum = sum + east;
         const T v = c * sum;
-        res[e] = (!COLCHK || col_in[e]) ? v : m[e];
+        res[e] = (EDGE == 0 || col_in[e]) ? v : m[e];
     }
 }
 
@@ -229,19 +237,19 @@ __device__ __forceinline__ void stream_level(const T (&a)[V], const T (&m)[V], c
 // last three steps (a0, b0, x: oldest first) straight from the load ring;
 // w0[k], w1[k] hold the two latest rows of level k >= 1, older first. With
 // NACT == TL the level-TL row goes to `top`.
-template <typename T, int V, int TL, int NACT, bool COLCHK, bool ROWCHK>
+template <typename T, int V, int TL, int NACT, int EDGE, bool ROWCHK>
 __device__ __forceinline__ void stream_step(T (&w0)[TL][V], T (&w1)[TL][V], const T (&a0)[V], const T (&b0)[V],
                                             const T (&x)[V], T (&top)[V], int L, int dir, int H, T c,
                                             const bool (&col_in)[V]) {
     if constexpr (NACT >= 1) {
         T cur[V];
-        stream_level<T, V, COLCHK>(a0, b0, x, cur, c, !ROWCHK || (L - dir >= 1 && L - dir <= H - 2), col_in);
+        stream_level<T, V, EDGE>(a0, b0, x, cur, c, !ROWCHK || (L - dir >= 1 && L - dir <= H - 2), col_in);
 #pragma unroll
         for (int s = 2; s <= NACT; ++s) {
             const int r = L - dir * s;
             const bool row_in = !ROWCHK || (r >= 1 && r <= H - 2);
             T nv[V];
-            stream_level<T, V, COLCHK>(w0[s - 1], w1[s - 1], cur, nv, c, row_in, col_in);
+            stream_level<T, V, EDGE>(w0[s - 1], w1[s - 1], cur, nv, c, row_in, col_in);
 #pragma unroll
             for (int e = 0; e < V; ++e) {
                 w0[s - 1][e] = w1[s - 1][e];
@@ -267,17 +275,17 @@ __device__ __forceinline__ void stream_step(T (&w0)[TL][V], T (&w1)[TL][V], cons
 // which the hardware drops, and a step past the band (live == false) gets an
 // empty range. No lane branches, so the compiler can count every store in
 // flight and never waits for a younger load than the one a step reads.
-// Interior strips store whole vectors; edge strips store column by column.
+// EDGE 0 and 1 strips store whole vectors; EDGE 2 strips store column by column.
 constexpr uint32_t kDropOffset = 0x80000000u;  // past the end of any row range
 constexpr int kRawBufferConfig = 0x00020000;    // raw (untyped) buffer words, gfx9 family
 
-template <typename T, int V, bool COLCHK>
+template <typename T, int V, int EDGE>
 __device__ __forceinline__ void stream_store(T* __restrict__ out, int r, int64_t ld, int W, bool live,
                                              uint32_t voff_vec, const uint32_t (&voff_el)[V], const T (&top)[V]) {
     T* row = out + (int64_t)(live ? r : 1) * ld;  // a dead step's row may lie outside the grid
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc(row, 0, live ? W * (int)sizeof(T) : 0, kRawBufferConfig);
-    if constexpr (!COLCHK) {
+    if constexpr (EDGE < 2) {
         typedef int IV __attribute__((ext_vector_type(4)));
         static_assert(sizeof(T) * V == sizeof(IV), "one 16-byte vector per lane");
         typedef typename TVec<T, V>::type VT;
@@ -309,18 +317,18 @@ struct Ring {
 };
 
 // Steps 0 .. 2*TL-1: level s is complete from step 2s on.
-template <typename T, int V, int TL, int A, int K, bool COLCHK>
+template <typename T, int V, int TL, int A, int K, int EDGE>
 __device__ __forceinline__ void stream_prologue(T (&w0)[TL][V], T (&w1)[TL][V], T (&ring)[Ring<A>::P][V],
                                                 const T* __restrict__ in, int L0, int dir, int H, int W, int64_t ld,
                                                 int j0, T c, const bool (&col_in)[V]) {
     constexpr int P = Ring<A>::P;
     if constexpr (K < 2 * TL) {
         T unused[V];
-        stream_step<T, V, TL, K / 2, COLCHK, true>(w0, w1, ring[(K + P - 2) % P], ring[(K + P - 1) % P], ring[K % P],
+        stream_step<T, V, TL, K / 2, EDGE, true>(w0, w1, ring[(K + P - 2) % P], ring[(K + P - 1) % P], ring[K % P],
                                                    unused, L0 + dir * K, dir, H, c, col_in);
-        stream_load<T, V, COLCHK>(in, L0 + dir * (K + A), H, W, ld, j0, ring[(K + A) % P]);
+        stream_load<T, V, EDGE>(in, L0 + dir * (K + A), H, W, ld, j0, ring[(K + A) % P]);
         __builtin_amdgcn_sched_barrier(0);
-        stream_prologue<T, V, TL, A, K + 1, COLCHK>(w0, w1, ring, in, L0, dir, H, W, ld, j0, c, col_in);
+        stream_prologue<T, V, TL, A, K + 1, EDGE>(w0, w1, ring, in, L0, dir, H, W, ld, j0, c, col_in);
     }
 }
 
@@ -328,41 +336,58 @@ __device__ __forceinline__ void stream_prologue(T (&w0)[TL][V], T (&w1)[TL][V], 
 // level's two kept rows plus its new row (3). An unrolled group of U steps
 // therefore ends with every row back in the register it started in: no
 // copies, and no wait on a load other than the one a step reads.
-template <typename T, int V, int TL, int A, bool COLCHK>
+//
+// Wave priority follows progress: a wave starts at priority 3 and drops one
+// level after each quarter of its band. The hardware issues the oldest wave of
+// the highest priority first, so without this the oldest wave on a SIMD ran
+// ahead and the youngest finished its band alone, latency-bound; with it the
+// waves sharing a SIMD advance together and finish together.
+template <typename T, int V, int TL, int A, int EDGE>
 __device__ __forceinline__ void stream_band(const T* __restrict__ in, T* __restrict__ out, int H, int W, int64_t ld,
-                                            T c, int cs, int rb, int re, int dir) {
+                                            T c, int cs, int olo, int ohi, int rb, int re, int dir) {
     constexpr int P = Ring<A>::P;
     constexpr int U = Ring<A>::U;
-    constexpr int HALO = (TL + V - 1) / V * V;
-    constexpr int OW = 64 * V - 2 * HALO;
     const int lane = threadIdx.x;
     const int j0 = cs + lane * V;
     bool col_in[V];
 #pragma unroll
     for (int e = 0; e < V; ++e) col_in[e] = (j0 + e >= 1) && (j0 + e <= W - 2);
-    // store offsets (bytes within the row): the lane's output columns, else dropped
-    const int oc0 = cs + HALO;
-    const bool st_lane = (j0 >= oc0) && (j0 + V <= oc0 + OW);
+    // store offsets (bytes within the row): the lane's columns inside [olo, ohi), else dropped
+    const bool st_lane = (j0 >= olo) && (j0 + V <= ohi);
     const uint32_t voff_vec = st_lane ? (uint32_t)j0 * (uint32_t)sizeof(T) : kDropOffset;
     uint32_t voff_el[V];
 #pragma unroll
-    for (int e = 0; e < V; ++e) voff_el[e] = (st_lane && col_in[e]) ? (uint32_t)(j0 + e) * (uint32_t)sizeof(T) : kDropOffset;
+    for (int e = 0; e < V; ++e)
+        voff_el[e] = (j0 + e >= olo && j0 + e < ohi && col_in[e]) ? (uint32_t)(j0 + e) * (uint32_t)sizeof(T)
+                                                                   : kDropOffset;
 
     // step t loads row L0 + dir*t; the band's rows [rb, re) are stored
     const int L0 = dir > 0 ? rb - TL : re - 1 + TL;
     const int nsteps = (re - rb) + 2 * TL;
+    __builtin_amdgcn_s_setprio(3);
     T w0[TL][V], w1[TL][V];
     T ring[P][V];
 #pragma unroll
-    for (int i = 0; i < A; ++i) stream_load<T, V, COLCHK>(in, L0 + dir * i, H, W, ld, j0, ring[i]);
-    stream_prologue<T, V, TL, A, 0, COLCHK>(w0, w1, ring, in, L0, dir, H, W, ld, j0, c, col_in);
+    for (int i = 0; i < A; ++i) stream_load<T, V, EDGE>(in, L0 + dir * i, H, W, ld, j0, ring[i]);
+    stream_prologue<T, V, TL, A, 0, EDGE>(w0, w1, ring, in, L0, dir, H, W, ld, j0, c, col_in);
 
     // Groups of U steps; level rows of step t are L - dir*s for s = 1..TL and
     // leave [1, H-2] only where the loaded row is outside the grid. The last
     // group may run past the band (at most U-1 steps): those steps compute
     // rows that are not stored (and loads stay clamped to the grid).
     const int ngroups = (nsteps - 2 * TL + U - 1) / U;
+    int quarter = 0;
     for (int k = 0; k < ngroups; ++k) {
+        const int q = (4 * k) / ngroups;
+        if (q != quarter) {
+            quarter = q;
+            if (q == 1)
+                __builtin_amdgcn_s_setprio(2);
+            else if (q == 2)
+                __builtin_amdgcn_s_setprio(1);
+            else
+                __builtin_amdgcn_s_setprio(0);
+        }
         const int g = 2 * TL + k * U;
         const int La = L0 + dir * g, Lb = L0 + dir * (g + U - 1);
         const bool rowchk = min(La, Lb) < 0 || max(La, Lb) > H - 1;
@@ -372,13 +397,13 @@ __device__ __forceinline__ void stream_band(const T* __restrict__ in, T* __restr
             const int L = L0 + dir * (g + i);
             T top[V];
             if (!rowchk)
-                stream_step<T, V, TL, TL, COLCHK, false>(w0, w1, ring[(t + P - 2) % P], ring[(t + P - 1) % P],
-                                                         ring[t % P], top, L, dir, H, c, col_in);
+                stream_step<T, V, TL, TL, EDGE, false>(w0, w1, ring[(t + P - 2) % P], ring[(t + P - 1) % P],
+                                                       ring[t % P], top, L, dir, H, c, col_in);
             else
-                stream_step<T, V, TL, TL, COLCHK, true>(w0, w1, ring[(t + P - 2) % P], ring[(t + P - 1) % P],
-                                                        ring[t % P], top, L, dir, H, c, col_in);
-            stream_load<T, V, COLCHK>(in, L + dir * A, H, W, ld, j0, ring[(t + A) % P]);
-            stream_store<T, V, COLCHK>(out, L - dir * TL, ld, W, g + i < nsteps, voff_vec, voff_el, top);
+                stream_step<T, V, TL, TL, EDGE, true>(w0, w1, ring[(t + P - 2) % P], ring[(t + P - 1) % P],
+                                                      ring[t % P], top, L, dir, H, c, col_in);
+            stream_load<T, V, EDGE>(in, L + dir * A, H, W, ld, j0, ring[(t + A) % P]);
+            stream_store<T, V, EDGE>(out, L - dir * TL, ld, W, g + i < nsteps, voff_vec, voff_el, top);
             // keep steps apart: interleaving them only hoists lane shifts and
             // loads, which costs registers (occupancy) and gains nothing
             __builtin_amdgcn_sched_barrier(0);
@@ -386,22 +411,42 @@ __device__ __forceinline__ void stream_band(const T* __restrict__ in, T* __restr
     }
 }
 
+// Strip layout. Flush layout (flush != 0: W is a multiple of V and at least
+// 64*V): strip 0 loads columns [0, 64V) and stores [0, 64V - HALO); strip k
+// loads from k*OW and stores [k*OW + HALO, (k+1)*OW + HALO); the last strip
+// loads the grid's last 64V columns and stores [W - 64V + HALO, W). Only the
+// first and last strips touch a boundary column, and all loads stay inside the
+// grid. The last strip's stores may overlap its neighbour's: both compute the
+// same bits there. Otherwise (flush == 0) strip k loads from k*OW - HALO and
+// stores [k*OW, (k+1)*OW); the first and last strips load past the grid.
 template <typename T, int V, int TL, int A>
 __global__ __launch_bounds__(64) void sweep_stream_kernel(const T* __restrict__ in, T* __restrict__ out, int H, int W,
-                                                         int64_t ld, T c, uint32_t strips, int band) {
+                                                         int64_t ld, T c, uint32_t strips, int band, int flush) {
     constexpr int HALO = (TL + V - 1) / V * V;
     constexpr int OW = 64 * V - 2 * HALO;
     const uint32_t tile = xcd_tile_of_block(blockIdx.x, gridDim.x);
     const uint32_t bi = tile / strips;
     const uint32_t strip = tile - bi * strips;
-    const int cs = (int)strip * OW - HALO;  // first loaded column, a multiple of V
+    int cs, olo, ohi;  // first loaded column (a multiple of V), stored columns [olo, ohi)
+    if (flush) {
+        const bool last = strip == strips - 1;
+        cs = last ? W - 64 * V : (int)strip * OW;
+        olo = strip == 0 ? 0 : cs + HALO;
+        ohi = last ? W : cs + HALO + OW;
+    } else {
+        cs = (int)strip * OW - HALO;
+        olo = cs + HALO;
+        ohi = olo + OW;
+    }
     const int rb = 1 + (int)bi * band;
     const int re = min(rb + band, H - 1);
     const int dir = (bi & 1) ? -1 : 1;
     if (cs >= 1 && cs + 64 * V <= W - 1)
-        stream_band<T, V, TL, A, false>(in, out, H, W, ld, c, cs, rb, re, dir);
+        stream_band<T, V, TL, A, 0>(in, out, H, W, ld, c, cs, olo, ohi, rb, re, dir);
+    else if (flush)
+        stream_band<T, V, TL, A, 1>(in, out, H, W, ld, c, cs, olo, ohi, rb, re, dir);
     else
-        stream_band<T, V, TL, A, true>(in, out, H, W, ld, c, cs, rb, re, dir);
+        stream_band<T, V, TL, A, 2>(in, out, H, W, ld, c, cs, olo, ohi, rb, re, dir);
 }
 
 // END KERNEL SOURCE
@@ -441,11 +486,11 @@ void launch_tb(const T* in, T* out, int H, int W, int64_t ld, T c, hipStream_t s
 int g_tb_rows = 0;     // tuning hook: output rows per register tile (0: 8)
 int g_tb_variant = 0;  // 0: built-in (streaming), 1: register tile, 2: streaming
 int g_tb_band = 0;     // streaming: output rows per band (0: built-in)
-int g_tb_depth = 0;    // streaming: rows loaded ahead (0: built-in 4; 4 or 7)
+int g_tb_depth = 0;    // streaming: rows loaded ahead (0 or 4; loading 7 ahead measured no faster)
 
 constexpr int kStreamDepth = 4;
 constexpr int kMaxBlockLevels = 6;
-constexpr int kMaxStreamLevels = 8;
+constexpr int kMaxStreamLevels = 12;
 
 template <typename T, int V, int ROWS>
 void launch_levels_rows(const T* in, T* out, int H, int W, int64_t ld, T c, int levels, hipStream_t s) {
@@ -484,7 +529,10 @@ template <typename T, int V, int TL, int D>
 void launch_stream(const T* in, T* out, int H, int W, int64_t ld, T c, hipStream_t s) {
     constexpr int HALO = (TL + V - 1) / V * V;
     constexpr int OW = 64 * V - 2 * HALO;
-    const uint32_t strips = ceil_div(W - 1, OW);  // strip k stores columns [k*OW, (k+1)*OW)
+    const int flush = (W % V == 0 && W >= 64 * V) ? 1 : 0;
+    // flush: enough regular strips that the last (right-aligned) strip meets them; else strip k
+    // stores columns [k*OW, (k+1)*OW)
+    const uint32_t strips = flush ? ceil_div(W - 64 * V, OW) + 1 : ceil_div(W - 1, OW);
     int band = g_tb_band;
     if (band <= 0) {
         // Built-in: the tallest bands that still give every resident wave slot
@@ -493,11 +541,9 @@ void launch_stream(const T* in, T* out, int H, int W, int64_t ld, T c, hipStream
         static const int waves = resident_waves(reinterpret_cast<const void*>(&sweep_stream_kernel<T, V, TL, D>));
         const int64_t fit = std::max<int64_t>(1, (waves > 0 ? waves : 1024) / (int64_t)strips);
         band = (int)std::max<int64_t>(2 * TL, (H - 2 + fit - 1) / fit);
-        constexpr int U = Ring<D>::U;
-        band = (band + U - 1) / U * U;  // whole groups: no step past the band except in the last band
     }
     const uint32_t bands = ceil_div(H - 2, band);
-    sweep_stream_kernel<T, V, TL, D><<<strips * bands, 64, 0, s>>>(in, out, H, W, ld, c, strips, band);
+    sweep_stream_kernel<T, V, TL, D><<<strips * bands, 64, 0, s>>>(in, out, H, W, ld, c, strips, band, flush);
 }
 
 template <typename T, int V, int D>
@@ -510,7 +556,11 @@ void launch_stream_depth(const T* in, T* out, int H, int W, int64_t ld, T c, int
         case 5: launch_stream<T, V, 5, D>(in, out, H, W, ld, c, s); break;
         case 6: launch_stream<T, V, 6, D>(in, out, H, W, ld, c, s); break;
         case 7: launch_stream<T, V, 7, D>(in, out, H, W, ld, c, s); break;
-        default: launch_stream<T, V, 8, D>(in, out, H, W, ld, c, s); break;
+        case 8: launch_stream<T, V, 8, D>(in, out, H, W, ld, c, s); break;
+        case 9: launch_stream<T, V, 9, D>(in, out, H, W, ld, c, s); break;
+        case 10: launch_stream<T, V, 10, D>(in, out, H, W, ld, c, s); break;
+        case 11: launch_stream<T, V, 11, D>(in, out, H, W, ld, c, s); break;
+        default: launch_stream<T, V, 12, D>(in, out, H, W, ld, c, s); break;
     }
 }
 
@@ -521,10 +571,7 @@ void launch_levels(const T* in, T* out, int H, int W, int64_t ld, T c, int level
     const bool stream_fits = (int64_t)W * (int64_t)sizeof(T) < ((int64_t)1 << 30);
     if (g_tb_variant == 1 || (!stream_fits && levels <= kMaxBlockLevels))
         return launch_levels_block<T, V>(in, out, H, W, ld, c, levels, s);
-    switch (g_tb_depth > 0 ? g_tb_depth : kStreamDepth) {
-        case 7: launch_stream_depth<T, V, 7>(in, out, H, W, ld, c, levels, s); break;
-        default: launch_stream_depth<T, V, 4>(in, out, H, W, ld, c, levels, s); break;
-    }
+    launch_stream_depth<T, V, kStreamDepth>(in, out, H, W, ld, c, levels, s);
 }
 
 template <typename T>
@@ -545,14 +592,14 @@ sten_status run_tb(const T* u0, T* out, T* work, int64_t H, int64_t W, int64_t l
     const int h = (int)H, w = (int)W;
     const int64_t nring = 2 * W + 2 * (H - 2);
     tb_ring_copy_kernel<T><<<ceil_div(nring, 256), 256, 0, stream>>>(u0, out, need_work ? work : nullptr, h, w, ld);
-    // launch k (1-based) applies `lev` sweeps; the last launch must write `out`
+    // launch k (1-based) applies `lev` sweeps, the T sweeps split as evenly as the
+    // launch count allows (each at most tl); the last launch must write `out`
     const T* src = u0;
-    int done = 0;
+    const int base = T_ / launches, extra = T_ % launches;
     for (int k = 1; k <= launches; ++k) {
-        const int lev = std::min(tl, T_ - done);
+        const int lev = base + (k <= extra ? 1 : 0);
         T* dst = ((launches - k) % 2 == 0) ? out : work;
         launch_levels<T, VV>(src, dst, h, w, ld, c, lev, stream);
-        done += lev;
         src = dst;
     }
     return check_launch();
@@ -586,7 +633,7 @@ sten_status sten_jacobi5_f32_tb(const float* u0, float* out, float* work, int64_
 
 sten_status sten_tune_tb(int32_t variant, int32_t band, int32_t depth) {
     if (variant < 0 || variant > 2 || band < 0 || band > 65536) return STEN_ERR_ARG;
-    if (depth != 0 && depth != 4 && depth != 7) return STEN_ERR_ARG;
+    if (depth != 0 && depth != sten::kStreamDepth) return STEN_ERR_ARG;
     sten::g_tb_variant = variant;
     sten::g_tb_band = band;
     sten::g_tb_depth = depth;

@@ -92,15 +92,15 @@ def jacobi5_tb(u0: torch.Tensor, T: int, c: float = 0.25, levels: int = 2, out: 
 
 
 def set_schedule(levels: int) -> None:
-    """Sweeps per launch of `jacobi5` (1: one per launch; 2..8: temporal blocking; 0: built-in)."""
+    """Sweeps per launch of `jacobi5` (1: one per launch; 2..12: temporal blocking; 0: built-in)."""
     _lib.call("sten_tune_schedule", int(levels))
 
 
 def set_tb(variant: int = 0, band: int = 0, depth: int = 0) -> None:
     """Tuning hook for the temporally blocked kernels (0 everywhere restores the built-in choice).
 
-    variant: 1 = register tile (levels 1..6), 2 = streaming (levels 1..8);
-    band: output rows per streaming band; depth: rows the streaming kernel loads ahead (4 or 7).
+    variant: 1 = register tile (levels 1..6), 2 = streaming (levels 1..12);
+    band: output rows per streaming band; depth: rows the streaming kernel loads ahead (0 or 4).
     """
     _lib.call("sten_tune_tb", int(variant), int(band), int(depth))
 

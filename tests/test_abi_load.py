@@ -78,12 +78,13 @@ def test_tune_hooks_validate_and_restore(lib):
     assert lib.sten_tune_tb(3, 0, 0) == -1          # no such variant
     assert lib.sten_tune_tb(-1, 0, 0) == -1
     assert lib.sten_tune_tb(2, -1, 0) == -1         # negative band
-    assert lib.sten_tune_tb(2, 0, 3) == -1          # depth not 4 or 7
-    assert lib.sten_tune_tb(2, 17, 7) == 0
+    assert lib.sten_tune_tb(2, 0, 3) == -1          # depth not 0 or 4
+    assert lib.sten_tune_tb(2, 0, 7) == -1
+    assert lib.sten_tune_tb(2, 17, 4) == 0
     assert lib.sten_tune_tb(0, 0, 0) == 0
-    assert lib.sten_tune_schedule(9) == -1
+    assert lib.sten_tune_schedule(13) == -1
     assert lib.sten_tune_schedule(-1) == -1
-    assert lib.sten_tune_schedule(8) == 0
+    assert lib.sten_tune_schedule(12) == 0
     assert lib.sten_tune_schedule(0) == 0
     assert lib.sten_tune_tb_rows(5) == -1
     assert lib.sten_tune_tb_rows(0) == 0

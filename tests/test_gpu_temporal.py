@@ -1,7 +1,7 @@
 """Temporal blocking (several sweeps per HBM pass) is bit-identical to the oracle, via the C ABI.
 
 Both blocked kernels run: the register tile (levels 1..6) and the streaming
-kernel (levels 1..8, several band heights and load-ahead depths).
+kernel (levels 1..12, several band heights, both strip layouts).
 """
 
 import numpy as np
@@ -14,7 +14,7 @@ from workloads import large_f64, normal_grid
 pytestmark = pytest.mark.gpu
 
 BLOCK, STREAM = 1, 2
-VARIANTS = [("block", BLOCK, range(1, 7)), ("stream", STREAM, range(1, 9))]
+VARIANTS = [("block", BLOCK, range(1, 7)), ("stream", STREAM, range(1, 13))]
 
 
 @pytest.fixture(scope="module")
@@ -26,7 +26,8 @@ def ops():
     ops.set_tb(0, 0, 0)
 
 
-SHAPES = [(3, 3), (5, 7), (9, 130), (64, 64), (63, 65), (257, 1031), (130, 2049), (600, 3), (3, 600), (17, 250)]
+SHAPES = [(3, 3), (5, 7), (9, 130), (64, 64), (63, 65), (257, 1031), (130, 2049), (600, 3), (3, 600), (17, 250),
+          (41, 512), (12, 260)]
 TS = (1, 2, 3, 5, 10, 17)
 
 
@@ -48,17 +49,20 @@ def test_tb_bit_exact(ops, shape, dtype):
         ops.set_tb(0, 0, 0)
 
 
-@pytest.mark.parametrize("depth", [4, 7])
+@pytest.mark.parametrize("depth", [0, 4])
 @pytest.mark.parametrize("band", [1, 2, 7, 32, 1000])
 def test_tb_stream_band_and_depth(ops, band, depth):
-    """Band heights that leave a ragged last band, a band of one row, and one band for the whole grid."""
-    cases = [((131, 300), np.float64), ((67, 1030), np.float32), ((40, 2049), np.float64)]
+    """Band heights that leave a ragged last band, a band of one row, and one band for the whole grid;
+    widths that give the right-aligned strip layout (multiple of the vector width, >= 64 vectors) and
+    widths that do not."""
+    cases = [((131, 300), np.float64), ((67, 1030), np.float32), ((40, 2049), np.float64),
+             ((29, 1032), np.float32), ((33, 128), np.float64), ((30, 256), np.float32)]
     try:
         ops.set_tb(STREAM, band, depth)
         for shape, dtype in cases:
             u0 = normal_grid(*shape, seed=band + depth + shape[0], dtype=dtype)
             d = to_dev(u0)
-            for levels in (1, 3, 5, 8):
+            for levels in (1, 3, 5, 8, 10, 12):
                 T = 11
                 say(f"tb stream band={band} depth={depth} {shape} {dtype.__name__} levels={levels}")
                 got = to_host(ops.jacobi5_tb(d, T, levels=levels))
@@ -87,7 +91,7 @@ def test_tb_levels_out_of_range(ops):
             ops.jacobi5_tb(u0, 10, levels=7)
         ops.set_tb(STREAM, 0, 0)
         with pytest.raises(ops._lib.StenError):
-            ops.jacobi5_tb(u0, 10, levels=9)
+            ops.jacobi5_tb(u0, 10, levels=13)
         with pytest.raises(ops._lib.StenError):
             ops.jacobi5_tb(u0, 10, levels=0)
     finally:
@@ -100,7 +104,7 @@ def test_tb_full_size(ops):
     d = to_dev(u0)
     want = oracle.jacobi5(u0, 10)
     try:
-        for name, variant, levels_list in [("block", BLOCK, (2, 4, 5)), ("stream", STREAM, (2, 5, 8))]:
+        for name, variant, levels_list in [("block", BLOCK, (2, 4, 5)), ("stream", STREAM, (2, 5, 8, 10, 12))]:
             ops.set_tb(variant, 0, 0)
             for levels in levels_list:
                 say(f"tb {name} 4096 levels={levels} T=10")
