@@ -20,6 +20,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -205,8 +206,30 @@ std::string generate_source(const Program& prog) {
 }
 
 std::mutex g_mu;
-std::unordered_map<std::string, std::vector<char>> g_code;         // "arch\n" + source -> code object
-std::map<std::pair<int, std::string>, hipFunction_t> g_functions;  // (device, arch+source) -> kernel
+std::unordered_map<std::string, std::vector<char>> g_code;  // "arch\n" + source -> code object
+
+// A validated program, its generated source and its kernel per device, cached by
+// program text and slot counts, so a repeated launch neither parses nor
+// generates again.
+struct Prepared {
+    Program prog;
+    std::string src;
+    std::map<int, hipFunction_t> fn;  // device -> loaded kernel (modules stay loaded)
+};
+std::unordered_map<std::string, std::unique_ptr<Prepared>> g_prepared;
+constexpr size_t kMaxPrepared = 4096;
+
+// Parse and generate once per (text, nin, nout). Caller holds g_mu.
+Prepared* prepare_locked(const char* text, int nin, int nout) {
+    std::string key = std::to_string(nin) + "," + std::to_string(nout) + ":" + text;
+    auto it = g_prepared.find(key);
+    if (it != g_prepared.end()) return it->second.get();
+    auto p = std::make_unique<Prepared>();
+    if (!parse_program(text, nin, nout, &p->prog)) return nullptr;
+    p->src = generate_source(p->prog);
+    if (g_prepared.size() >= kMaxPrepared) g_prepared.clear();  // bound the cache; loaded modules stay valid
+    return g_prepared.emplace(std::move(key), std::move(p)).first->second.get();
+}
 
 // Compile (or fetch) the code object of `src` for `arch`. Caller holds g_mu.
 sten_status compile_locked(const std::string& src, const std::string& arch, const std::vector<char>** code) {
@@ -276,9 +299,13 @@ const char* sten_expr_log(void) { return sten::g_log.c_str(); }
 sten_status sten_expr_source(const char* program, int32_t nin, int32_t nout, char* buf, size_t cap, size_t* len) {
     using namespace sten;
     if (program == nullptr || nin < 1 || nin > kExprMaxIn || nout < 1 || nout > kExprMaxOut) return STEN_ERR_ARG;
-    Program prog;
-    if (!parse_program(program, nin, nout, &prog)) return STEN_ERR_ARG;
-    const std::string src = generate_source(prog);
+    std::string src;
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        Prepared* p = prepare_locked(program, nin, nout);
+        if (p == nullptr) return STEN_ERR_ARG;
+        src = p->src;
+    }
     if (len != nullptr) *len = src.size();
     if (buf != nullptr && cap > 0) {
         const size_t n = std::min(cap - 1, src.size());
@@ -291,11 +318,11 @@ sten_status sten_expr_source(const char* program, int32_t nin, int32_t nout, cha
 sten_status sten_expr_compile(const char* program, int32_t nin, int32_t nout, const char* arch) {
     using namespace sten;
     if (program == nullptr || nin < 1 || nin > kExprMaxIn || nout < 1 || nout > kExprMaxOut) return STEN_ERR_ARG;
-    Program prog;
-    if (!parse_program(program, nin, nout, &prog)) return STEN_ERR_ARG;
     std::lock_guard<std::mutex> lock(g_mu);
+    Prepared* p = prepare_locked(program, nin, nout);
+    if (p == nullptr) return STEN_ERR_ARG;
     const std::vector<char>* code = nullptr;
-    return compile_locked(generate_source(prog), arch != nullptr ? arch : "gfx950", &code);
+    return compile_locked(p->src, arch != nullptr ? arch : "gfx950", &code);
 }
 
 sten_status sten_expr_run(const char* program, const sten_expr_in* ins, int32_t nin, const sten_expr_out* outs,
@@ -306,68 +333,69 @@ sten_status sten_expr_run(const char* program, const sten_expr_in* ins, int32_t 
     if (rows > INT32_MAX || cols > INT32_MAX) return STEN_ERR_ARG;
     const int64_t bpr = (cols + kExprBlock - 1) / kExprBlock;
     if (rows * bpr > INT32_MAX) return STEN_ERR_ARG;
-    Program prog;
-    if (!parse_program(program, nin, nout, &prog)) return STEN_ERR_ARG;
-    if (rows == 0 || cols == 0) return STEN_OK;
-    // every load stays inside its slot's declared extent
-    for (const auto& e : prog.outs)
-        for (const Token& t : e)
-            if (t.kind == Token::LOAD) {
-                const sten_expr_in& s = ins[t.slot];
-                if (t.di < s.row_lo || rows - 1 + t.di > s.row_hi || t.dj < s.col_lo || cols - 1 + t.dj > s.col_hi) {
-                    g_log = "expression program: a load leaves its input's extent";
-                    return STEN_ERR_ARG;
-                }
-            }
-    for (int k = 0; k < nin; ++k) {
-        if (ins[k].ld < 1 || ins[k].row_lo > ins[k].row_hi || ins[k].col_lo > ins[k].col_hi) return STEN_ERR_ARG;
-        if (ins[k].col_hi - ins[k].col_lo >= ins[k].ld) return STEN_ERR_ARG;
-    }
-    for (int o = 0; o < nout; ++o)
-        if (outs[o].base == nullptr || outs[o].ld < cols) return STEN_ERR_ARG;
-    // outputs overlap no input extent and no other output
-    for (int o = 0; o < nout; ++o) {
-        uintptr_t olo, ohi;
-        span_of(outs[o].base, outs[o].ld, 0, rows - 1, 0, cols - 1, &olo, &ohi);
-        for (int k = 0; k < nin; ++k) {
-            uintptr_t ilo, ihi;
-            span_of(ins[k].base, ins[k].ld, ins[k].row_lo, ins[k].row_hi, ins[k].col_lo, ins[k].col_hi, &ilo, &ihi);
-            if (olo < ihi && ilo < ohi) return STEN_ERR_ALIAS;
-        }
-        for (int q = 0; q < o; ++q) {
-            uintptr_t qlo, qhi;
-            span_of(outs[q].base, outs[q].ld, 0, rows - 1, 0, cols - 1, &qlo, &qhi);
-            if (olo < qhi && qlo < ohi) return STEN_ERR_ALIAS;
-        }
-    }
-    for (int k = 0; k < nin; ++k)
-        if (!is_device_ptr(ins[k].base)) return STEN_ERR_PTR;
-    for (int o = 0; o < nout; ++o)
-        if (!is_device_ptr(outs[o].base)) return STEN_ERR_PTR;
-
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(e);
-    const std::string arch = device_arch(dev);
-    if (arch.empty()) return hip_fail(hipGetLastError());
-    const std::string src = generate_source(prog);
+    // One lock from parsing to the kernel lookup: the prepared program (owned by the cache) stays valid
+    // while it is read. HIP calls made under it (pointer queries, compile, module load) call nothing back.
     hipFunction_t fn = nullptr;
     {
         std::lock_guard<std::mutex> lock(g_mu);
-        auto key = std::make_pair(dev, arch + "\n" + src);
-        auto it = g_functions.find(key);
-        if (it != g_functions.end()) {
+        Prepared* prep = prepare_locked(program, nin, nout);
+        if (prep == nullptr) return STEN_ERR_ARG;
+        if (rows == 0 || cols == 0) return STEN_OK;
+        // every load stays inside its slot's declared extent
+        for (const auto& e : prep->prog.outs)
+            for (const Token& t : e)
+                if (t.kind == Token::LOAD) {
+                    const sten_expr_in& s = ins[t.slot];
+                    if (t.di < s.row_lo || rows - 1 + t.di > s.row_hi || t.dj < s.col_lo ||
+                        cols - 1 + t.dj > s.col_hi) {
+                        g_log = "expression program: a load leaves its input's extent";
+                        return STEN_ERR_ARG;
+                    }
+                }
+        for (int k = 0; k < nin; ++k) {
+            if (ins[k].ld < 1 || ins[k].row_lo > ins[k].row_hi || ins[k].col_lo > ins[k].col_hi) return STEN_ERR_ARG;
+            if (ins[k].col_hi - ins[k].col_lo >= ins[k].ld) return STEN_ERR_ARG;
+        }
+        for (int o = 0; o < nout; ++o)
+            if (outs[o].base == nullptr || outs[o].ld < cols) return STEN_ERR_ARG;
+        // outputs overlap no input extent and no other output
+        for (int o = 0; o < nout; ++o) {
+            uintptr_t olo, ohi;
+            span_of(outs[o].base, outs[o].ld, 0, rows - 1, 0, cols - 1, &olo, &ohi);
+            for (int k = 0; k < nin; ++k) {
+                uintptr_t ilo, ihi;
+                span_of(ins[k].base, ins[k].ld, ins[k].row_lo, ins[k].row_hi, ins[k].col_lo, ins[k].col_hi, &ilo,
+                        &ihi);
+                if (olo < ihi && ilo < ohi) return STEN_ERR_ALIAS;
+            }
+            for (int q = 0; q < o; ++q) {
+                uintptr_t qlo, qhi;
+                span_of(outs[q].base, outs[q].ld, 0, rows - 1, 0, cols - 1, &qlo, &qhi);
+                if (olo < qhi && qlo < ohi) return STEN_ERR_ALIAS;
+            }
+        }
+        for (int k = 0; k < nin; ++k)
+            if (!is_device_ptr(ins[k].base)) return STEN_ERR_PTR;
+        for (int o = 0; o < nout; ++o)
+            if (!is_device_ptr(outs[o].base)) return STEN_ERR_PTR;
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return hip_fail(e);
+        auto it = prep->fn.find(dev);
+        if (it != prep->fn.end()) {
             fn = it->second;
         } else {
+            const std::string arch = device_arch(dev);
+            if (arch.empty()) return hip_fail(hipGetLastError());
             const std::vector<char>* code = nullptr;
-            sten_status st = compile_locked(src, arch, &code);
+            sten_status st = compile_locked(prep->src, arch, &code);
             if (st != STEN_OK) return st;
             hipModule_t mod;
             e = hipModuleLoadData(&mod, code->data());
             if (e != hipSuccess) return hip_fail(e);
             e = hipModuleGetFunction(&fn, mod, "sten_expr_kernel");
             if (e != hipSuccess) return hip_fail(e);
-            g_functions.emplace(key, fn);  // modules stay loaded for the process's lifetime
+            prep->fn.emplace(dev, fn);  // modules stay loaded for the process's lifetime
         }
     }
     ExprArgs a{};
@@ -383,7 +411,8 @@ sten_status sten_expr_run(const char* program, const sten_expr_in* ins, int32_t 
     a.cols = (int32_t)cols;
     a.bpr = (int32_t)bpr;
     void* params[] = {&a};
-    e = hipModuleLaunchKernel(fn, (unsigned)(rows * bpr), 1, 1, kExprBlock, 1, 1, 0, stream, params, nullptr);
+    const hipError_t e = hipModuleLaunchKernel(fn, (unsigned)(rows * bpr), 1, 1, kExprBlock, 1, 1, 0, stream, params,
+                                               nullptr);
     if (e != hipSuccess) return hip_fail(e);
     return STEN_OK;
 }

@@ -231,6 +231,9 @@ class Context:
         self.nodes: list[Node] = []
         self.asts: dict[str, int] = {}
         self.stats = {"nodes": 0, "flushes": 0, "launch_groups": 0, "fused_nodes": 0}
+        # per array (uid): indices of the current DAG's nodes that write it / read it
+        self._writers: dict[int, list] = {}
+        self._readers: dict[int, list] = {}
 
     def create_array(self, shape) -> Array:
         return Array(self, shape)
@@ -251,18 +254,21 @@ class Context:
         ast = _structure(expr, {})
         self.asts[ast] = self.asts.get(ast, 0) + 1
         node = Node(out, region, expr, ins, ast)
-        for k, m in enumerate(self.nodes):
-            true_dep = any(a is m.out for a in ins)
-            anti_dep = any(a is out for a in m.ins)
-            out_dep = m.out is out
-            if true_dep or anti_dep or out_dep:
-                node.deps.add(k)
+        in_uids = {a.uid for a in ins}
+        for u in in_uids:                                       # true dependences (read after write)
+            node.deps.update(self._writers.get(u, ()))
+        node.deps.update(self._readers.get(out.uid, ()))       # anti dependences (write after read)
+        node.deps.update(self._writers.get(out.uid, ()))       # output dependences (write after write)
         node.depth = 1 + max((self.nodes[k].depth for k in node.deps), default=0)
         if node.depth > self.max_depth:
             self.flush()
             node.deps = set()
             node.depth = 1
+        k = len(self.nodes)
         self.nodes.append(node)
+        for u in in_uids:
+            self._readers.setdefault(u, []).append(k)
+        self._writers.setdefault(out.uid, []).append(k)
         self.stats["nodes"] += 1
 
     def depth(self) -> int:
@@ -296,6 +302,8 @@ class Context:
             if len(g) > 1:
                 self.stats["fused_nodes"] += len(g)
         self.nodes = []
+        self._writers.clear()
+        self._readers.clear()
         self.stats["flushes"] += 1
 
     def sync(self) -> None:
@@ -433,21 +441,25 @@ def build_program(nodes: list) -> tuple:
 
 
 def split_for_limits(nodes: list) -> list:
-    """Consecutive chunks of a fused group that fit one generated kernel's slot and output limits."""
-    chunks, cur = [], []
+    """A fused group as consecutive chunks that each fit one generated kernel's slot and output limits;
+    returns build_program's result for each chunk."""
+    progs = []
+    cur: list = []
+    prog = None
     for n in nodes:
-        trial = cur + [n]
-        _, ins, outs, _, _ = build_program(trial)
-        if cur and (len(ins) > EXPR_MAX_IN or len(outs) > EXPR_MAX_OUT):
-            chunks.append(cur)
-            trial = [n]
-        cur = trial
-    if cur:
-        chunks.append(cur)
-    for c in chunks:
-        if len(build_program(c)[1]) > EXPR_MAX_IN:
+        trial = build_program(cur + [n])
+        if cur and (len(trial[1]) > EXPR_MAX_IN or len(trial[2]) > EXPR_MAX_OUT):
+            progs.append(prog)
+            cur, trial = [n], build_program([n])
+        else:
+            cur = cur + [n]
+        prog = trial
+    if prog is not None:
+        progs.append(prog)
+    for p in progs:
+        if len(p[1]) > EXPR_MAX_IN:
             raise NotImplementedError(f"an expression reads more than {EXPR_MAX_IN} slices of distinct arrays")
-    return chunks
+    return progs
 
 
 # ---------------------------------------------------------------------------
@@ -465,6 +477,7 @@ class GpuBackend:
         self.torch = torch
         self.ops = ops
         self.device = device or torch.device("cuda")
+        self._programs: dict = {}
 
     def alloc(self, shape):
         return self.torch.zeros(shape, dtype=self.torch.float64, device=self.device)
@@ -505,8 +518,16 @@ class GpuBackend:
             s = match_star(n)
             self.ops.star(s[0].data, [s[1]], outs=[n.out.data])
             return
-        for chunk in split_for_limits(group):
-            text, ins, outs, rows, cols = build_program(chunk)
+        # programs depend only on the nodes' ASTs, regions and arrays: cache them (iterations that
+        # swap arrays alternate between a few keys)
+        key = tuple((n.ast, n.region, tuple(a.uid for a in n.ins), n.out.uid) for n in group)
+        progs = self._programs.get(key)
+        if progs is None:
+            progs = split_for_limits(group)
+            if len(self._programs) > 4096:
+                self._programs.clear()
+            self._programs[key] = progs
+        for text, ins, outs, rows, cols in progs:
             self.ops.expr_run(text, [(a.data, r0, c0) for a, r0, c0 in ins],
                               [(a.data, r0, c0) for a, r0, c0 in outs], rows, cols)
 

@@ -252,8 +252,7 @@ def test_frontend_cavity_programs_compile():
 
         def run(self, group):
             if fe.node_kind(group[0]) == "expr":
-                for chunk in fe.split_for_limits(group):
-                    text, ins, outs, _, _ = fe.build_program(chunk)
+                for text, ins, outs, _, _ in fe.split_for_limits(group):
                     self.programs.add((text, len(ins), len(outs)))
             super().run(group)
 
