@@ -203,6 +203,46 @@ def bench_paper_shape(ops, args, n: int = 16384, T: int = 1000) -> dict:
     return res
 
 
+def bench_hbm_check(ops, args, n: int = 8192, T: int = 100) -> dict:
+    """The plain step at 8192^2 FP64: a ping-pong pair of 2 x 512 MiB does not fit the 256 MB Infinity
+    Cache (MALL), so HBM serves every byte; at 4096^2 (2 x 128 MiB) part of the traffic is MALL-served.
+    A device copy of the same size gives the practical ceiling at this size."""
+    import torch
+
+    from workloads import large_f64
+
+    log(f"[bench] HBM check {n}x{n}")
+    u0 = torch.from_numpy(large_f64(0, n)).to("cuda:0")
+    out = torch.empty_like(u0)
+    work = torch.empty_like(u0)
+    interior = (n - 2) ** 2
+    res = {"workload": f"{n}x{n} FP64 N(0,1) seed 0, {T} sweeps per step"}
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    sec = timed(lambda: out.copy_(u0), 10)
+    res["device_copy_GBps"] = round(2 * 8 * n * n / sec / 1e9, 1)
+    for name, sched in (("default_schedule", 0), ("single_sweep_schedule", 1)):
+        ops.set_schedule(sched)
+        sec = timed(lambda: ops.jacobi5(u0, T, out=out, work=work), 3)
+        res[name] = {"ms_per_step": round(sec * 1e3, 3), "us_per_sweep": round(sec / T * 1e6, 2),
+                     "effective_GBps_at_16B": round(16.0 * interior * T / sec / 1e9, 1)}
+    ops.set_schedule(0)
+    del u0, out, work
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_batch(ops, T: int, args) -> dict:
     """1024 FP32 grids (point counts log-uniform in [2^8, 2^16], seed 0), T sweeps each,
     in one persistent launch replayed from a HIP graph; launch configuration autotuned."""
@@ -695,6 +735,7 @@ def main() -> int:
         rec["extensions"] = {
             "mixed_hilo": bench_mixed(ops, n, T, args, single_sec_per_step, sec_per_step),
             "paper_shape": bench_paper_shape(ops, args),
+            "hbm_check": bench_hbm_check(ops, args),
             "batched": bench_batch(ops, T, args),
             "tiled": bench_tiled(ops, n, T, args, single_sec_per_step),
             "temporal_blocking": bench_temporal(ops, n, T, args, single_sec_per_step),

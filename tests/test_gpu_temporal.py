@@ -134,3 +134,11 @@ def test_tb_unsupported_falls_back(ops):
     t.copy_(to_dev(u0))
     say("tb odd ld fallback")
     assert np.array_equal(to_host(ops.jacobi5_tb(t, 5, levels=2)), oracle.jacobi5(u0, 5))
+
+
+def test_f32_full_size_default_schedule(ops):
+    """4096 x 4096 FP32 through the plain call (built-in schedule: 8 sweeps per launch) vs the FP32 oracle."""
+    u0 = large_f64(0).astype(np.float32)
+    say("f32 4096 T=10 built-in schedule")
+    got = to_host(ops.jacobi5(to_dev(u0), 10))
+    assert np.array_equal(got, oracle.jacobi5(u0, 10, dtype=np.float32))
