@@ -113,6 +113,29 @@ def test_strided_and_misaligned_views(ops, dtype):
     assert np.array_equal(to_host(ops.jacobi5(odd, 5)), oracle.jacobi5(u0, 5, dtype=dtype))
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_strided_view_wide(ops, dtype):
+    """ld > W with W a multiple of the vector width and >= 64 vectors (the strip layout aligned with the
+    grid's sides), and with W just above it."""
+    rng_grid = normal_grid(70, 300, seed=6, dtype=dtype)
+    big = to_dev(rng_grid)
+    for W in (256, 260, 296):
+        view = big[:, :W]
+        u0 = rng_grid[:, :W]
+        for T in (1, 3, 11):
+            say(f"wide view {dtype.__name__} W={W} T={T}")
+            assert np.array_equal(to_host(ops.jacobi5(view, T)), oracle.jacobi5(u0, T, dtype=dtype))
+
+
+def test_odd_large_shape(ops):
+    """4097 x 4095 FP64 (odd sizes, past 2^24 points): whole-grid bit-exact for odd and even T."""
+    u0 = normal_grid(4097, 4095, seed=7)
+    d = to_dev(u0)
+    for T in (1, 2, 3, 10):
+        say(f"4097x4095 T={T}")
+        assert np.array_equal(to_host(ops.jacobi5(d, T)), oracle.jacobi5(u0, T)), f"T={T}"
+
+
 def test_single_sweep_entry_keeps_ring(ops):
     import torch
 
