@@ -24,6 +24,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -48,14 +49,18 @@ def log(msg: str) -> None:
 
 
 def source_sha(path: str) -> str:
-    """Hash of the kernel's source region (between the BEGIN/END KERNEL SOURCE markers)."""
-    with open(path, "rb") as f:
+    """Hash of the kernel's code: the region between the BEGIN/END KERNEL SOURCE markers with `//`
+    comments, trailing blanks and blank lines removed, so that only a change of code invalidates
+    counters taken on it."""
+    with open(path, encoding="utf-8") as f:
         text = f.read()
-    a = text.find(b"BEGIN KERNEL SOURCE")
-    b = text.find(b"END KERNEL SOURCE")
+    a = text.find("BEGIN KERNEL SOURCE")
+    b = text.find("END KERNEL SOURCE")
     if a >= 0 and b > a:
         text = text[a:b]
-    return hashlib.sha256(text).hexdigest()[:16]
+    lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines()]
+    code = "\n".join(ln for ln in lines if ln.strip())
+    return hashlib.sha256(code.encode()).hexdigest()[:16]
 
 
 def load_traffic(path: str, src: str):
