@@ -323,21 +323,30 @@ def bench_batch(ops, T: int, args) -> dict:
     }
 
 
-def bench_tiled(ops, n: int, T: int, args, plain_sec_per_step: float) -> dict:
-    """The plain FP64 step on the same grid split into tiles with ghost exchange (one GPU)."""
+def bench_tiled(ops, n: int, T: int, args, plain_sec_per_step: float, blocked_sec_per_step: float) -> dict:
+    """The plain FP64 step on the same grid split into tiles with ghost exchange (one GPU): depth-1 ghosts
+    (one exchange and one kernel per tile per sweep) and deep ghosts (one exchange and one blocked launch
+    over all tiles per chunk of up to g sweeps)."""
     import torch
 
     from workloads import large_f64
 
     log("[bench] tiled execution")
     u0 = torch.from_numpy(large_f64(0, n)).to("cuda:0")
+    want = ops.jacobi5(u0, T)
     comm = torch.cuda.Stream()
     res = {}
-    for pr, pc in ((2, 2), (4, 4)):
-        t = ops.TiledGrid(n, n, pr, pc, comm_stream=comm)
+    cases = ((2, 2, 1, "packed", True), (4, 4, 1, "packed", True), (2, 2, 10, "packed", True),
+             (2, 2, 10, "packed", False), (2, 2, 10, "direct", False), (4, 4, 10, "direct", False),
+             (8, 8, 10, "direct", False))
+    for pr, pc, g, mode, two_streams in cases:
+        t = ops.TiledGrid(n, n, pr, pc, comm_stream=comm if two_streams else None, ghost=g, exchange=mode)
         t.scatter(u0)
+        t.run(T)
+        same = bool(torch.equal(t.gather(), want))
         t.run(2)
         torch.cuda.synchronize()
+        before = t.stats()
         reps = max(3, args.steps // 4)
         t0 = time.perf_counter()
         for _ in range(reps):
@@ -345,14 +354,20 @@ def bench_tiled(ops, n: int, T: int, args, plain_sec_per_step: float) -> dict:
         torch.cuda.synchronize()
         sec = (time.perf_counter() - t0) / reps
         st = t.stats()
-        res[f"{pr}x{pc}"] = {
+        res[f"{pr}x{pc}_ghost{g}_{mode}_{'2' if two_streams else '1'}stream"] = {
             "ms_per_step": round(sec * 1e3, 4),
             "effective_GBps": round(16.0 * (n - 2) ** 2 * T / sec / 1e9, 1),
-            "overhead_vs_single_grid_single_sweep": round(sec / plain_sec_per_step, 3),
-            "sweep_launches_per_step": st["sweep_launches"] // (reps + 1) if reps else None,
+            "vs_single_grid_single_sweep": round(sec / plain_sec_per_step, 3),
+            "vs_single_grid_default_schedule": round(sec / blocked_sec_per_step, 3),
+            "exchanges_per_step": (st["exchanges"] - before["exchanges"]) // reps,
+            "sweep_launches_per_step": (st["sweep_launches"] - before["sweep_launches"]) // reps,
+            "bit_identical_to_single_grid": same,
         }
-    res["workload"] = (f"{n}x{n} FP64 N(0,1) seed 0, {T} sweeps per step, tiles with depth-1 ghosts; "
-                       "pack/unpack on a second stream, per-tile sweep kernels")
+    res["workload"] = (f"{n}x{n} FP64 N(0,1) seed 0, {T} sweeps per step; pr x pc tiles with ghost frames of "
+                       "depth g; exchange packed (pack + unpack kernels through send buffers) or direct (one "
+                       "copy kernel), on a second stream (2stream) or the compute stream (1stream); g = 1: one "
+                       "exchange and one sweep kernel per tile per sweep; g > 1: one exchange and one blocked "
+                       "launch over all tiles per chunk of up to g sweeps")
     return res
 
 
@@ -742,7 +757,7 @@ def main() -> int:
             "paper_shape": bench_paper_shape(ops, args),
             "hbm_check": bench_hbm_check(ops, args),
             "batched": bench_batch(ops, T, args),
-            "tiled": bench_tiled(ops, n, T, args, single_sec_per_step),
+            "tiled": bench_tiled(ops, n, T, args, single_sec_per_step, sec_per_step),
             "temporal_blocking": bench_temporal(ops, n, T, args, single_sec_per_step),
             "frontend": bench_frontend(ops, args),
             "adjoint": bench_adjoint(10, args),

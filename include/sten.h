@@ -400,33 +400,68 @@ sten_status sten_reduce_f64(const double* partials, int64_t n, double* out, hipS
 /* ------------------------------------------------------------------------ */
 /*
  * The paper's data layout and DAG execution (Section III-C): an H x W FP64
- * grid split into pr x pc tiles, each with its owned block, a depth-1 ghost
- * frame (the ghost depth of the five-point stencil), two buffers and one send
- * buffer per neighbour edge. Before a sweep reads an array, its ghosts are
- * refreshed when its local generation epoch differs from its ghost epoch:
- * pack and unpack kernels on the communication stream, ordered against the
- * compute stream by a compute event and a communication event. Results are
- * bit-identical to sten_jacobi5_f64 on the whole grid for any tiling.
+ * grid split into pr x pc tiles, each with its owned block, a ghost frame of
+ * depth g (1 is the ghost depth of the five-point stencil) and two buffers.
+ * Before a sweep reads an array, its ghosts are refreshed when its local
+ * generation epoch differs from its ghost epoch, by exchange kernels on the
+ * communication stream, ordered against the compute stream by a compute event
+ * and a communication event. A frame of depth g > 1 lets every tile run up to
+ * g sweeps between exchanges; its exchange also carries the g x g corner
+ * blocks between diagonal neighbours. Results are bit-identical to
+ * sten_jacobi5_f64 on the whole grid for any tiling, depth and mode.
  */
 typedef struct sten_tiled_s* sten_tiled_handle;
 
-/* Device workspace bytes for a tiling (0 when the tiling is invalid:
- * H, W, pr, pc < 1 or more tiles than rows/columns). */
+/* Exchange modes. PACKED: the paper's scheme, a pack kernel into one send
+ * buffer per neighbour (in the workspace) and an unpack kernel into the ghost
+ * frames. DIRECT: one kernel copies each neighbour's boundary block straight
+ * into the ghost frame (no send buffers). */
+typedef enum { STEN_TILED_PACKED = 0, STEN_TILED_DIRECT = 1 } sten_tiled_mode;
+
+/* Device workspace bytes for a tiling with ghost depth 1, packed mode (0 when
+ * the tiling is invalid: H, W, pr, pc < 1 or more tiles than rows/columns). */
 size_t sten_tiled_workspace_bytes(int64_t H, int64_t W, int32_t pr, int32_t pc);
 
+/* Device workspace bytes for a tiling with ghost depth `ghost` (1..12) and
+ * exchange mode `mode`; 0 when the tiling is invalid: as above, or a tile
+ * thinner than `ghost` across an edge it shares with a neighbour, or an
+ * unknown mode, or (ghost > 1) rows of 2^27 elements or more. */
+size_t sten_tiled_workspace_bytes_ex(int64_t H, int64_t W, int32_t pr, int32_t pc, int32_t ghost, int32_t mode);
+
 /* Create the tiling inside dev_ws (device memory, 256-byte aligned, at least
- * sten_tiled_workspace_bytes). Tile (a, b) owns rows [a H/pr, (a+1) H/pr) and
- * columns [b W/pc, (b+1) W/pc) (integer division). Host-side handle. */
+ * sten_tiled_workspace_bytes). Ghost depth 1, packed mode. Tile (a, b) owns
+ * rows [a H/pr, (a+1) H/pr) and columns [b W/pc, (b+1) W/pc) (integer
+ * division). Host-side handle. */
 sten_status sten_tiled_create(int64_t H, int64_t W, int32_t pr, int32_t pc, void* dev_ws, size_t ws_bytes,
                               sten_tiled_handle* out);
+
+/* As sten_tiled_create with ghost depth `ghost` (1..12) and exchange mode
+ * `mode`: sten_tiled_run then exchanges once per at most `ghost` sweeps.
+ * STEN_ERR_ARG for an invalid tiling (see sten_tiled_workspace_bytes_ex),
+ * STEN_ERR_WORKSPACE when ws_bytes is too small. */
+sten_status sten_tiled_create_ex(int64_t H, int64_t W, int32_t pr, int32_t pc, int32_t ghost, int32_t mode,
+                                 void* dev_ws, size_t ws_bytes, sten_tiled_handle* out);
+
+/* Host-only check of a tiling's plan (no HIP call): lays the workspace out at a
+ * stand-in address and checks that every exchange copy, owned block and sweep
+ * view lies inside its buffer, that each message matches its ghost block, and
+ * that views are 16-byte aligned. info[0..3] = tiles, messages per exchange,
+ * exchange kernel launches, workspace bytes (n >= 4). STEN_OK when the plan
+ * passes; STEN_ERR_ARG for an invalid tiling; STEN_ERR_UNSUPPORTED if a check
+ * fails (sten_tiled_create_ex runs the same check and refuses such a plan). */
+sten_status sten_tiled_plan_check(int64_t H, int64_t W, int32_t pr, int32_t pc, int32_t ghost, int32_t mode,
+                                  int64_t* info, int32_t n);
 
 /* Load a grid u (row stride ld) into both buffers of every tile; ghosts become
  * stale (epochs advance). */
 sten_status sten_tiled_scatter(sten_tiled_handle t, const double* u, int64_t ld, hipStream_t stream);
 
-/* T sweeps with coefficient c: per sweep, a ghost exchange of the array being
- * read (when stale) on `comm`, then one sweep kernel per tile on `compute`.
- * The streams may be the same. */
+/* T sweeps with coefficient c, in ceil(T / g) chunks of at most g sweeps (split
+ * as evenly as that count allows): per chunk, a ghost exchange of the array
+ * being read (when stale) on `comm`, then on `compute` either one sweep kernel
+ * per tile (chunks of one sweep) or one launch of the streaming blocked kernel
+ * over all tiles (per 32 tiles). The streams may be the same (then no events
+ * are recorded). */
 sten_status sten_tiled_run(sten_tiled_handle t, int32_t T, double c, hipStream_t compute, hipStream_t comm);
 
 /* Refresh the current array's ghosts if stale (a second call in a row is skipped). */
@@ -436,7 +471,8 @@ sten_status sten_tiled_exchange(sten_tiled_handle t, hipStream_t compute, hipStr
 sten_status sten_tiled_gather(sten_tiled_handle t, double* u, int64_t ld, hipStream_t stream);
 
 /* stats[0..4] = tiles, exchanges performed, exchanges skipped (epochs equal),
- * sweep kernel launches, strips per exchange. */
+ * sweep kernel launches, messages per exchange; stats[5] = ghost depth and
+ * stats[6] = mode when n >= 7. */
 sten_status sten_tiled_stats(sten_tiled_handle t, int64_t* stats, int32_t n);
 
 /* Free the host-side handle (the workspace stays the caller's). */

@@ -56,4 +56,19 @@ __host__ __device__ inline uint32_t xcd_tile_of_block(uint32_t b, uint32_t nb) {
 
 inline uint32_t ceil_div(int64_t a, int64_t b) { return (uint32_t)((a + b - 1) / b); }
 
+// One grid of a multi-grid launch: an H x W grid with row stride ld, read from
+// `in`, written to `out` (interior only).
+template <typename T>
+struct GridView {
+    const T* in;
+    T* out;
+    int H, W;
+    int64_t ld;
+};
+
+// Streaming blocked kernel on several FP64 grids at once (temporal.hip), up to
+// kMaxStreamGridsPerLaunch grids per launch.
+constexpr int kMaxStreamGridsPerLaunch = 32;
+void launch_stream_grids_f64(const GridView<double>* views, int n, double c, int levels, hipStream_t s);
+
 }  // namespace sten

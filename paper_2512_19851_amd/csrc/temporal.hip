@@ -420,12 +420,12 @@ __device__ __forceinline__ void stream_band(const T* __restrict__ in, T* __restr
 // grid. The last strip's stores may overlap its neighbour's: both compute the
 // same bits there. Otherwise (flush == 0) strip k loads from k*OW - HALO and
 // stores [k*OW, (k+1)*OW); the first and last strips load past the grid.
+// Workgroup `tile` of a grid walks band tile / strips of strip tile % strips.
 template <typename T, int V, int TL, int A>
-__global__ __launch_bounds__(64) void sweep_stream_kernel(const T* __restrict__ in, T* __restrict__ out, int H, int W,
-                                                         int64_t ld, T c, uint32_t strips, int band, int flush) {
+__device__ __forceinline__ void stream_tile(const T* __restrict__ in, T* __restrict__ out, int H, int W, int64_t ld,
+                                            T c, uint32_t strips, int band, int flush, uint32_t tile) {
     constexpr int HALO = (TL + V - 1) / V * V;
     constexpr int OW = 64 * V - 2 * HALO;
-    const uint32_t tile = xcd_tile_of_block(blockIdx.x, gridDim.x);
     const uint32_t bi = tile / strips;
     const uint32_t strip = tile - bi * strips;
     int cs, olo, ohi;  // first loaded column (a multiple of V), stored columns [olo, ohi)
@@ -448,6 +448,42 @@ __global__ __launch_bounds__(64) void sweep_stream_kernel(const T* __restrict__ 
         stream_band<T, V, TL, A, 1>(in, out, H, W, ld, c, cs, olo, ohi, rb, re, dir);
     else
         stream_band<T, V, TL, A, 2>(in, out, H, W, ld, c, cs, olo, ohi, rb, re, dir);
+}
+
+template <typename T, int V, int TL, int A>
+__global__ __launch_bounds__(64) void sweep_stream_kernel(const T* __restrict__ in, T* __restrict__ out, int H, int W,
+                                                         int64_t ld, T c, uint32_t strips, int band, int flush) {
+    stream_tile<T, V, TL, A>(in, out, H, W, ld, c, strips, band, flush, xcd_tile_of_block(blockIdx.x, gridDim.x));
+}
+
+// Several grids in one launch: grid k owns the workgroups [first, first +
+// strips * bands) of the launch, numbered after the XCD-aware map, and runs
+// them as the one-grid kernel would. Grids are independent (no aliasing).
+template <typename T>
+struct StreamGrid {
+    const T* in;
+    T* out;
+    int64_t ld;
+    int H, W;
+    uint32_t strips, first;
+    int band, flush;
+};
+
+constexpr int kMaxStreamGrids = kMaxStreamGridsPerLaunch;
+
+template <typename T>
+struct StreamGrids {
+    StreamGrid<T> g[kMaxStreamGrids];
+    int n;
+};
+
+template <typename T, int V, int TL, int A>
+__global__ __launch_bounds__(64) void sweep_stream_grids_kernel(const StreamGrids<T> grids, T c) {
+    const uint32_t b = xcd_tile_of_block(blockIdx.x, gridDim.x);
+    int k = 0;
+    while (k + 1 < grids.n && b >= grids.g[k + 1].first) ++k;
+    const StreamGrid<T>& g = grids.g[k];
+    stream_tile<T, V, TL, A>(g.in, g.out, g.H, g.W, g.ld, c, g.strips, g.band, g.flush, b - g.first);
 }
 
 // END KERNEL SOURCE
@@ -565,6 +601,58 @@ void launch_stream_depth(const T* in, T* out, int H, int W, int64_t ld, T c, int
     }
 }
 
+// One launch of TL sweeps on each of n independent grids (n <= kMaxStreamGrids).
+// Band heights follow the one-grid rule with the strips of all grids together,
+// so the whole launch fits the device's resident wave slots in one round.
+template <typename T, int V, int TL, int D>
+void launch_stream_grids(const GridView<T>* views, int n, T c, hipStream_t s) {
+    constexpr int HALO = (TL + V - 1) / V * V;
+    constexpr int OW = 64 * V - 2 * HALO;
+    StreamGrids<T> args{};
+    args.n = n;
+    int64_t all_strips = 0;
+    for (int k = 0; k < n; ++k) {
+        StreamGrid<T>& g = args.g[k];
+        g.in = views[k].in;
+        g.out = views[k].out;
+        g.ld = views[k].ld;
+        g.H = views[k].H;
+        g.W = views[k].W;
+        g.flush = (g.W % V == 0 && g.W >= 64 * V) ? 1 : 0;
+        g.strips = g.flush ? ceil_div(g.W - 64 * V, OW) + 1 : ceil_div(g.W - 1, OW);
+        all_strips += g.strips;
+    }
+    static const int waves =
+        resident_waves(reinterpret_cast<const void*>(&sweep_stream_grids_kernel<T, V, TL, D>));
+    const int64_t fit = std::max<int64_t>(1, (waves > 0 ? waves : 1024) / std::max<int64_t>(1, all_strips));
+    uint32_t first = 0;
+    for (int k = 0; k < n; ++k) {
+        StreamGrid<T>& g = args.g[k];
+        g.band = g_tb_band > 0 ? g_tb_band : (int)std::max<int64_t>(2 * TL, (g.H - 2 + fit - 1) / fit);
+        g.first = first;
+        first += g.strips * ceil_div(g.H - 2, g.band);
+    }
+    if (first > 0) sweep_stream_grids_kernel<T, V, TL, D><<<first, 64, 0, s>>>(args, c);
+}
+
+template <typename T, int V, int D>
+void launch_stream_grids_depth(const GridView<T>* views, int n, T c, int levels, hipStream_t s) {
+    switch (levels) {
+        case 1: launch_stream_grids<T, V, 1, D>(views, n, c, s); break;
+        case 2: launch_stream_grids<T, V, 2, D>(views, n, c, s); break;
+        case 3: launch_stream_grids<T, V, 3, D>(views, n, c, s); break;
+        case 4: launch_stream_grids<T, V, 4, D>(views, n, c, s); break;
+        case 5: launch_stream_grids<T, V, 5, D>(views, n, c, s); break;
+        case 6: launch_stream_grids<T, V, 6, D>(views, n, c, s); break;
+        case 7: launch_stream_grids<T, V, 7, D>(views, n, c, s); break;
+        case 8: launch_stream_grids<T, V, 8, D>(views, n, c, s); break;
+        case 9: launch_stream_grids<T, V, 9, D>(views, n, c, s); break;
+        case 10: launch_stream_grids<T, V, 10, D>(views, n, c, s); break;
+        case 11: launch_stream_grids<T, V, 11, D>(views, n, c, s); break;
+        default: launch_stream_grids<T, V, 12, D>(views, n, c, s); break;
+    }
+}
+
 // One blocked launch of `levels` sweeps.
 template <typename T, int V>
 void launch_levels(const T* in, T* out, int H, int W, int64_t ld, T c, int levels, hipStream_t s) {
@@ -607,6 +695,15 @@ sten_status run_tb(const T* u0, T* out, T* work, int64_t H, int64_t W, int64_t l
 }
 
 }  // namespace
+
+// `levels` sweeps (1..12) on each of n independent grids, in launches of up to
+// kMaxStreamGrids grids. Each grid: H, W >= 3, in and out 16-byte aligned, ld
+// even and W * 8 below 2^30 bytes; the caller checks these.
+void launch_stream_grids_f64(const GridView<double>* views, int n, double c, int levels, hipStream_t s) {
+    for (int k = 0; k < n; k += kMaxStreamGrids)
+        launch_stream_grids_depth<double, 2, kStreamDepth>(views + k, std::min(n - k, kMaxStreamGrids), c, levels,
+                                                           s);
+}
 
 // Entry used by the plain calls when they pick the blocked schedule.
 sten_status run_tb_f64(const double* u0, double* out, double* work, int64_t H, int64_t W, int64_t ld, int32_t T,

@@ -3,22 +3,34 @@
 // tiles on one device.
 //
 //  * The H x W grid is split into pr x pc tiles ("chares"). Each tile holds
-//    its owned block plus a depth-1 ghost frame (the ghost depth of the
-//    five-point stencil), in two buffers (the ping-pong pair), and one send
-//    buffer per edge that has a neighbour.
+//    its owned block plus a ghost frame of depth g on every side, in two
+//    buffers (the ping-pong pair). g = 1 is the ghost depth of the five-point
+//    stencil; a deeper frame lets a tile run up to g sweeps between exchanges.
 //  * Before a sweep reads an array, its ghosts are refreshed if the array's
 //    local generation epoch differs from its ghost epoch: on the
-//    communication stream, after waiting for the compute event, a pack kernel
-//    copies every tile's boundary strips into its send buffers and an unpack
-//    kernel copies each neighbour's send buffer into the ghost frame; the
-//    communication event then gates the compute stream. On one GPU the unpack
-//    reads the neighbour's send buffer directly (the transfer is the copy
-//    itself); across GPUs it would read a received copy.
-//  * Each tile's sweep is the plain sweep kernel applied to a view of its
-//    buffer: the view spans the owned block plus the ghost rows/columns on the
-//    sides that have a neighbour, so the view's interior is exactly the
-//    owned points that are interior points of the whole grid. Results are
-//    bit-identical to the single-grid method.
+//    communication stream, after waiting for the compute event, the exchange
+//    kernels run, and the communication event then gates the compute stream
+//    (no events when the two streams are the same).
+//  * Exchange modes. Packed (the paper's scheme): a pack kernel copies each
+//    tile's boundary blocks into one send buffer per neighbour and an unpack
+//    kernel copies each neighbour's send buffer into the ghost frame; on one
+//    GPU the unpack reads the neighbour's send buffer directly (the transfer
+//    is the copy itself), across GPUs it would read a received copy. Direct:
+//    one kernel copies each neighbour's boundary block straight into the ghost
+//    frame, as a peer store into the neighbour's memory would.
+//  * g sweeps depend on the diagonal neighbours too (the cone of g sweeps of a
+//    five-point stencil is a diamond of radius g), so for g > 1 the exchange
+//    also carries the g x g corner blocks between diagonal neighbours. For
+//    g = 1 the corners are never read.
+//  * Each tile sweeps a view of its buffer: the owned block plus the whole
+//    ghost frame on the sides that have a neighbour. On a side without one the
+//    view ends at the owned boundary row or column, which is the grid's fixed
+//    ring. A sweep of the view leaves the view's own ring unchanged, so after
+//    s <= g sweeps a point at distance d from a ghost side is exact when
+//    d >= s: every owned point is. Results are bit-identical to the
+//    single-grid method. Chunks of one sweep use the plain sweep kernel per
+//    tile; chunks of s > 1 sweeps use one launch of the streaming blocked
+//    kernel over all tile views.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,23 +42,31 @@ namespace sten {
 
 void launch_sweep_f64_internal(const double* in, double* out, int H, int W, int64_t ld, double c, hipStream_t s);
 
+constexpr int kMaxGhost = 12;
+
 namespace {
 
+// A rows x cols rectangle copy between two row-major regions.
 struct alignas(16) Strip {
     const double* src;
     double* dst;
-    int64_t src_stride;
-    int64_t dst_stride;
-    int32_t n, pad;
+    int64_t src_ld;
+    int64_t dst_ld;
+    int32_t rows, cols;
 };
 
-// Copy strips: strip s = blockIdx.y; elements by threads of blockIdx.x.
+// Copy strips: strip s = blockIdx.y; its elements by the threads of blockIdx.x.
 __global__ void strip_copy_kernel(const Strip* __restrict__ strips, int nstrips) {
     const int s = blockIdx.y;
     if (s >= nstrips) return;
     const Strip st = strips[s];
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < st.n; k += gridDim.x * blockDim.x)
-        st.dst[(int64_t)k * st.dst_stride] = st.src[(int64_t)k * st.src_stride];
+    const int64_t total = (int64_t)st.rows * st.cols;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = k / st.cols;
+        const int64_t j = k - i * st.cols;
+        st.dst[i * st.dst_ld + j] = st.src[i * st.src_ld + j];
+    }
 }
 
 // Global grid rows/cols [r0, r0+h) x [c0, c0+w) <-> owned block of a tile buffer.
@@ -63,12 +83,19 @@ __global__ void block_copy_kernel(const double* __restrict__ src, int64_t src_ld
     }
 }
 
+// Neighbour directions: 0 north, 1 south, 2 west, 3 east, 4 north-west,
+// 5 north-east, 6 south-west, 7 south-east (north = lower row index).
+constexpr int kDirs = 8;
+constexpr int kDirRow[kDirs] = {-1, 1, 0, 0, -1, -1, 1, 1};
+constexpr int kDirCol[kDirs] = {0, 0, -1, 1, -1, 1, -1, 1};
+constexpr int kOpposite[kDirs] = {1, 0, 3, 2, 7, 6, 5, 4};
+
 struct Tile {
     int r0, c0, h, w;       // owned block in grid coordinates
     int64_t ldt;            // row stride of the tile buffers (elements, even)
-    double* buf[2];         // (h + 2) x ldt each; owned (i, j) at [(i + 1) * ldt + (j + 1)]
-    double* send[4];        // per edge: 0 north, 1 south, 2 west, 3 east (NULL when no neighbour)
-    int nb[4];              // neighbour tile index per edge, -1 when none
+    double* buf[2];         // (h + 2g) x ldt each; owned (i, j) at [(i + g) * ldt + (j + g)]
+    double* send[kDirs];    // packed mode: send buffer per neighbour (NULL when none)
+    int nb[kDirs];          // neighbour tile index per direction, -1 when none
 };
 
 }  // namespace
@@ -76,13 +103,15 @@ struct Tile {
 
 struct sten_tiled_s {
     int64_t H = 0, W = 0;
-    int pr = 0, pc = 0;
+    int pr = 0, pc = 0, g = 1;
+    int mode = 0;  // 0: packed (pack + unpack through send buffers), 1: direct
     std::vector<sten::Tile> tiles;
-    sten::Strip* d_pack[2] = {nullptr, nullptr};    // per buffer
-    sten::Strip* d_unpack[2] = {nullptr, nullptr};
-    int n_pack = 0, n_unpack = 0, max_strip = 0;
+    // per buffer k: the copy tables of one exchange (packed: pack then unpack; direct: copy)
     std::vector<sten::Strip> h_pack[2], h_unpack[2];
-    int cur = 0;                 // buffer holding the current state
+    sten::Strip* d_pack[2] = {nullptr, nullptr};
+    sten::Strip* d_unpack[2] = {nullptr, nullptr};
+    int n_strips = 0, max_strip = 0;  // messages per exchange, largest (elements)
+    int cur = 0;                      // buffer holding the current state
     int64_t local_epoch[2] = {0, 0};
     int64_t ghost_epoch[2] = {0, 0};
     int64_t n_exchanges = 0, n_skipped = 0, n_sweep_launches = 0;
@@ -95,19 +124,27 @@ namespace {
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Byte layout of the workspace: tile buffers, send buffers, then the strip tables.
-struct Layout {
-    std::vector<size_t> buf_off[2], send_off[4];
-    size_t tables_off = 0, total = 0;
-};
-
 int split(int64_t n, int parts, int k) { return (int)((n * k) / parts); }
 
-Layout plan_layout(int64_t H, int64_t W, int pr, int pc, std::vector<Tile>& tiles, int& nstrips) {
-    Layout L;
-    tiles.clear();
-    size_t off = 0;
-    nstrips = 0;
+// A region of the workspace (bytes from its base).
+struct Region {
+    size_t off, bytes;
+};
+
+// Byte layout of the workspace: tile buffers, send buffers, then the strip tables.
+struct Layout {
+    std::vector<size_t> buf_off[2], send_off;  // send_off[tile * 8 + direction]
+    std::vector<Region> regions;  // every buffer, for the bounds check
+    size_t buf_bytes_total = 0;
+    size_t tables_off = 0, table_slots = 0, total = 0;
+};
+
+// Tiles of the H x W grid, or an empty vector if the tiling is invalid for ghost depth g:
+// a tile must be at least g deep across every edge it shares with a neighbour.
+std::vector<Tile> make_tiles(int64_t H, int64_t W, int pr, int pc, int g) {
+    std::vector<Tile> tiles;
+    if (H < 1 || W < 1 || pr < 1 || pc < 1 || pr > H || pc > W || g < 1 || g > kMaxGhost) return tiles;
+    if (H > INT32_MAX / 2 || W > INT32_MAX / 2) return tiles;
     for (int a = 0; a < pr; ++a) {
         for (int b = 0; b < pc; ++b) {
             Tile t{};
@@ -115,59 +152,196 @@ Layout plan_layout(int64_t H, int64_t W, int pr, int pc, std::vector<Tile>& tile
             t.c0 = split(W, pc, b);
             t.h = split(H, pr, a + 1) - t.r0;
             t.w = split(W, pc, b + 1) - t.c0;
-            t.ldt = (int64_t)align_up((size_t)t.w + 2, 2);
-            t.nb[0] = a > 0 ? (a - 1) * pc + b : -1;
-            t.nb[1] = a < pr - 1 ? (a + 1) * pc + b : -1;
-            t.nb[2] = b > 0 ? a * pc + b - 1 : -1;
-            t.nb[3] = b < pc - 1 ? a * pc + b + 1 : -1;
+            if ((pr > 1 && t.h < g) || (pc > 1 && t.w < g)) return {};
+            t.ldt = (int64_t)align_up((size_t)t.w + 2 * g, 2);
+            for (int d = 0; d < kDirs; ++d) {
+                const int na = a + kDirRow[d], nbc = b + kDirCol[d];
+                const bool corner = kDirRow[d] != 0 && kDirCol[d] != 0;
+                // corner blocks are read only by chunks of more than one sweep
+                const bool used = !corner || g > 1;
+                t.nb[d] = (used && na >= 0 && na < pr && nbc >= 0 && nbc < pc) ? na * pc + nbc : -1;
+            }
             tiles.push_back(t);
         }
     }
+    return tiles;
+}
+
+// A rectangle of a tile buffer (buffer rows/cols).
+struct Rect {
+    int row, col, rows, cols;
+};
+
+// The g-deep block of tile t's owned points next to its side or corner d.
+Rect owned_block(const Tile& t, int d, int g) {
+    Rect r{};
+    r.row = kDirRow[d] < 0 ? g : (kDirRow[d] > 0 ? t.h : g);
+    r.rows = kDirRow[d] == 0 ? t.h : g;
+    r.col = kDirCol[d] < 0 ? g : (kDirCol[d] > 0 ? t.w : g);
+    r.cols = kDirCol[d] == 0 ? t.w : g;
+    return r;
+}
+
+// The part of tile t's ghost frame on its side or corner d.
+Rect ghost_block(const Tile& t, int d, int g) {
+    Rect r{};
+    r.row = kDirRow[d] < 0 ? 0 : (kDirRow[d] > 0 ? g + t.h : g);
+    r.rows = kDirRow[d] == 0 ? t.h : g;
+    r.col = kDirCol[d] < 0 ? 0 : (kDirCol[d] > 0 ? g + t.w : g);
+    r.cols = kDirCol[d] == 0 ? t.w : g;
+    return r;
+}
+
+Layout plan_layout(const std::vector<Tile>& tiles, int g, int mode) {
+    Layout L;
+    size_t off = 0;
+    int nstrips = 0;
     for (int k = 0; k < 2; ++k) L.buf_off[k].resize(tiles.size());
-    for (int e = 0; e < 4; ++e) L.send_off[e].resize(tiles.size());
+    L.send_off.assign(tiles.size() * kDirs, 0);
     for (size_t t = 0; t < tiles.size(); ++t) {
         const Tile& T = tiles[t];
         for (int k = 0; k < 2; ++k) {
             // +2 elements of slack so the sweep view can start 16-byte aligned
+            const size_t bytes = ((size_t)(T.h + 2 * g) * T.ldt + 2) * sizeof(double);
             L.buf_off[k][t] = off;
-            off = align_up(off + ((size_t)(T.h + 2) * T.ldt + 2) * sizeof(double), 256);
+            L.regions.push_back(Region{off, bytes});
+            off = align_up(off + bytes, 256);
         }
-        for (int e = 0; e < 4; ++e) {
-            L.send_off[e][t] = off;
-            if (T.nb[e] >= 0) {
-                ++nstrips;
-                off = align_up(off + (size_t)(e < 2 ? T.w : T.h) * sizeof(double), 256);
-            }
+        for (int d = 0; d < kDirs; ++d) {
+            if (T.nb[d] < 0) continue;
+            ++nstrips;
+            if (mode != 0) continue;
+            const Rect r = owned_block(T, d, g);
+            const size_t bytes = (size_t)r.rows * r.cols * sizeof(double);
+            L.send_off[t * kDirs + d] = off;
+            L.regions.push_back(Region{off, bytes});
+            off = align_up(off + bytes, 256);
         }
     }
     L.tables_off = off;
-    off += 4 * (size_t)std::max(nstrips, 1) * sizeof(Strip);
+    // 2 buffers x 2 tables, each sized for every message of an exchange
+    L.table_slots = (size_t)std::max(nstrips, 1);
+    off += 4 * L.table_slots * sizeof(Strip);
     L.total = align_up(off, 256);
     return L;
 }
 
-// View of a tile buffer whose interior is the tile's owned grid-interior points.
+// View of a tile buffer: the owned block plus the ghost frame on the sides that have a neighbour.
 struct View {
     int64_t off;  // element offset from the buffer base
     int vh, vw;   // view rows/cols
 };
 
-View tile_view(const Tile& t, int64_t H, int64_t W) {
-    const int top = (t.r0 == 0) ? 1 : 0;
-    const int bottom = (t.r0 + t.h == H) ? t.h : t.h + 1;
-    const int left = (t.c0 == 0) ? 1 : 0;
-    const int right = (t.c0 + t.w == W) ? t.w : t.w + 1;
-    return View{(int64_t)top * t.ldt + left, bottom - top + 1, right - left + 1};
+View tile_view(const Tile& t, int g) {
+    const int top = t.nb[0] >= 0 ? 0 : g;
+    const int bottom = t.nb[1] >= 0 ? t.h + 2 * g : t.h + g;
+    const int left = t.nb[2] >= 0 ? 0 : g;
+    const int right = t.nb[3] >= 0 ? t.w + 2 * g : t.w + g;
+    return View{(int64_t)top * t.ldt + left, bottom - top, right - left};
+}
+
+double* at(const Tile& t, int k, const Rect& r) { return t.buf[k] + (int64_t)r.row * t.ldt + r.col; }
+
+// Fill tile pointers and copy tables for a workspace at `base` (pointers are only computed here).
+void build_plan(sten_tiled_s* p, const Layout& L, char* base) {
+    const int g = p->g;
+    for (size_t t = 0; t < p->tiles.size(); ++t) {
+        Tile& T = p->tiles[t];
+        const View v = tile_view(T, g);
+        for (int k = 0; k < 2; ++k) {
+            // shift the buffer so that the view start lands on a 16-byte boundary
+            double* b = (double*)(base + L.buf_off[k][t]);
+            T.buf[k] = b + (v.off % 2 ? 1 : 0);
+        }
+        for (int d = 0; d < kDirs; ++d)
+            T.send[d] = (p->mode == 0 && T.nb[d] >= 0) ? (double*)(base + L.send_off[t * kDirs + d]) : nullptr;
+    }
+    p->max_strip = 0;
+    for (int k = 0; k < 2; ++k) {
+        p->h_pack[k].clear();
+        p->h_unpack[k].clear();
+        for (const Tile& T : p->tiles) {
+            for (int d = 0; d < kDirs; ++d) {
+                if (T.nb[d] < 0) continue;
+                const Tile& N = p->tiles[T.nb[d]];
+                const Rect src = owned_block(N, kOpposite[d], g);  // what the neighbour sends toward T
+                const Rect dst = ghost_block(T, d, g);
+                if (p->mode == 0) {
+                    // the neighbour packs its block into its send buffer toward T; T unpacks it
+                    double* sb = N.send[kOpposite[d]];
+                    p->h_pack[k].push_back(Strip{at(N, k, src), sb, N.ldt, src.cols, src.rows, src.cols});
+                    p->h_unpack[k].push_back(Strip{sb, at(T, k, dst), src.cols, T.ldt, dst.rows, dst.cols});
+                } else {
+                    p->h_pack[k].push_back(Strip{at(N, k, src), at(T, k, dst), N.ldt, T.ldt, dst.rows, dst.cols});
+                }
+                p->max_strip = std::max(p->max_strip, dst.rows * dst.cols);
+            }
+        }
+    }
+    p->n_strips = (int)p->h_pack[0].size();
+    Strip* tables = (Strip*)(base + L.tables_off);
+    for (int k = 0; k < 2; ++k) {
+        p->d_pack[k] = tables + (size_t)(2 * k) * L.table_slots;
+        p->d_unpack[k] = tables + (size_t)(2 * k + 1) * L.table_slots;
+    }
+}
+
+// True if [ptr, ptr + bytes) lies inside one region of the workspace at `base`.
+bool inside(const Layout& L, const char* base, const void* ptr, size_t bytes) {
+    const char* q = (const char*)ptr;
+    if (q < base) return false;
+    const size_t off = (size_t)(q - base);
+    for (const Region& r : L.regions)
+        if (off >= r.off && off + bytes <= r.off + r.bytes) return true;
+    return false;
+}
+
+size_t rect_bytes(int64_t rows, int64_t cols, int64_t ld) {
+    return rows <= 0 || cols <= 0 ? 0 : (size_t)((rows - 1) * ld + cols) * sizeof(double);
+}
+
+// Host check that every copy and every sweep view stays inside its buffer, that a
+// message and its ghost block agree in shape, and that views are 16-byte aligned.
+bool plan_in_bounds(const sten_tiled_s* p, const Layout& L, const char* base) {
+    for (int k = 0; k < 2; ++k) {
+        if (p->h_pack[k].size() > L.table_slots) return false;
+        if (p->mode == 0 && p->h_unpack[k].size() != p->h_pack[k].size()) return false;
+        if (p->mode != 0 && !p->h_unpack[k].empty()) return false;
+        for (const auto* tab : {&p->h_pack[k], &p->h_unpack[k]}) {
+            for (const Strip& s : *tab) {
+                if (s.rows < 1 || s.cols < 1 || s.cols > s.src_ld || s.cols > s.dst_ld) return false;
+                if (!inside(L, base, s.src, rect_bytes(s.rows, s.cols, s.src_ld))) return false;
+                if (!inside(L, base, s.dst, rect_bytes(s.rows, s.cols, s.dst_ld))) return false;
+            }
+        }
+        for (size_t i = 0; i < p->h_unpack[k].size(); ++i) {
+            const Strip& a = p->h_pack[k][i];
+            const Strip& b = p->h_unpack[k][i];
+            if (a.dst != b.src || a.rows != b.rows || a.cols != b.cols) return false;
+        }
+    }
+    for (const Tile& T : p->tiles) {
+        const View v = tile_view(T, p->g);
+        if (v.vw > T.ldt) return false;
+        for (int k = 0; k < 2; ++k) {
+            const double* a = T.buf[k] + v.off;
+            if (!inside(L, base, a, rect_bytes(v.vh, v.vw, T.ldt))) return false;
+            if ((size_t)((const char*)a - base) % 16 != 0) return false;
+            // the owned block (scatter and gather)
+            if (!inside(L, base, T.buf[k] + (int64_t)p->g * T.ldt + p->g, rect_bytes(T.h, T.w, T.ldt)))
+                return false;
+        }
+    }
+    return true;
 }
 
 sten_status upload_tables(sten_tiled_s* p, hipStream_t s) {
     for (int k = 0; k < 2; ++k) {
-        if (p->n_pack > 0) {
-            hipError_t e = hipMemcpyAsync(p->d_pack[k], p->h_pack[k].data(), p->n_pack * sizeof(Strip),
+        for (int u = 0; u < 2; ++u) {
+            const std::vector<Strip>& h = u ? p->h_unpack[k] : p->h_pack[k];
+            if (h.empty()) continue;
+            hipError_t e = hipMemcpyAsync(u ? p->d_unpack[k] : p->d_pack[k], h.data(), h.size() * sizeof(Strip),
                                           hipMemcpyHostToDevice, s);
-            if (e != hipSuccess) return hip_fail(e);
-            e = hipMemcpyAsync(p->d_unpack[k], p->h_unpack[k].data(), p->n_unpack * sizeof(Strip),
-                               hipMemcpyHostToDevice, s);
             if (e != hipSuccess) return hip_fail(e);
         }
     }
@@ -180,20 +354,66 @@ sten_status exchange(sten_tiled_s* p, int k, hipStream_t compute, hipStream_t co
         ++p->n_skipped;
         return STEN_OK;
     }
-    if (p->n_pack > 0) {
-        hipError_t e = hipEventRecord(p->ev_compute, compute);
-        if (e == hipSuccess) e = hipStreamWaitEvent(comm, p->ev_compute, 0);
-        if (e != hipSuccess) return hip_fail(e);
+    if (p->n_strips > 0) {
+        const bool two = comm != compute;
+        hipError_t e = hipSuccess;
+        if (two) {
+            e = hipEventRecord(p->ev_compute, compute);
+            if (e == hipSuccess) e = hipStreamWaitEvent(comm, p->ev_compute, 0);
+            if (e != hipSuccess) return hip_fail(e);
+        }
         const uint32_t gx = (uint32_t)std::min(64, std::max(1, (p->max_strip + 255) / 256));
-        strip_copy_kernel<<<dim3(gx, p->n_pack), 256, 0, comm>>>(p->d_pack[k], p->n_pack);
-        strip_copy_kernel<<<dim3(gx, p->n_unpack), 256, 0, comm>>>(p->d_unpack[k], p->n_unpack);
-        e = hipEventRecord(p->ev_comm, comm);
-        if (e == hipSuccess) e = hipStreamWaitEvent(compute, p->ev_comm, 0);
-        if (e != hipSuccess) return hip_fail(e);
+        const int n = p->n_strips;
+        strip_copy_kernel<<<dim3(gx, n), 256, 0, comm>>>(p->d_pack[k], n);
+        if (p->mode == 0) strip_copy_kernel<<<dim3(gx, n), 256, 0, comm>>>(p->d_unpack[k], n);
+        if (two) {
+            e = hipEventRecord(p->ev_comm, comm);
+            if (e == hipSuccess) e = hipStreamWaitEvent(compute, p->ev_comm, 0);
+            if (e != hipSuccess) return hip_fail(e);
+        }
     }
     p->ghost_epoch[k] = p->local_epoch[k];
     ++p->n_exchanges;
     return check_launch();
+}
+
+// s sweeps of every tile from buffer src to buffer 1 - src.
+void sweep_tiles(sten_tiled_s* p, int src, int s, double c, hipStream_t compute) {
+    const int dst = 1 - src;
+    if (s == 1) {
+        for (const Tile& t : p->tiles) {
+            const View v = tile_view(t, p->g);
+            if (v.vh < 3 || v.vw < 3) continue;
+            launch_sweep_f64_internal(t.buf[src] + v.off, t.buf[dst] + v.off, v.vh, v.vw, t.ldt, c, compute);
+            ++p->n_sweep_launches;
+        }
+        return;
+    }
+    std::vector<GridView<double>> views;
+    for (const Tile& t : p->tiles) {
+        const View v = tile_view(t, p->g);
+        if (v.vh < 3 || v.vw < 3) continue;
+        views.push_back(GridView<double>{t.buf[src] + v.off, t.buf[dst] + v.off, v.vh, v.vw, t.ldt});
+    }
+    if (views.empty()) return;
+    launch_stream_grids_f64(views.data(), (int)views.size(), c, s, compute);
+    p->n_sweep_launches += ((int64_t)views.size() + kMaxStreamGridsPerLaunch - 1) / kMaxStreamGridsPerLaunch;
+}
+
+sten_status make_plan(int64_t H, int64_t W, int pr, int pc, int g, int mode, sten_tiled_s* p, Layout& L) {
+    if (mode != 0 && mode != 1) return STEN_ERR_ARG;
+    p->tiles = make_tiles(H, W, pr, pc, g);
+    if (p->tiles.empty()) return STEN_ERR_ARG;
+    // the streaming kernel addresses a row with 32-bit byte offsets
+    if (g > 1 && (W + 2 * g) * (int64_t)sizeof(double) >= ((int64_t)1 << 30)) return STEN_ERR_UNSUPPORTED;
+    p->H = H;
+    p->W = W;
+    p->pr = pr;
+    p->pc = pc;
+    p->g = g;
+    p->mode = mode;
+    L = plan_layout(p->tiles, g, mode);
+    return STEN_OK;
 }
 
 }  // namespace
@@ -201,96 +421,70 @@ sten_status exchange(sten_tiled_s* p, int k, hipStream_t compute, hipStream_t co
 
 extern "C" {
 
+size_t sten_tiled_workspace_bytes_ex(int64_t H, int64_t W, int32_t pr, int32_t pc, int32_t ghost, int32_t mode) {
+    sten_tiled_s plan;
+    sten::Layout L;
+    if (sten::make_plan(H, W, pr, pc, ghost, mode, &plan, L) != STEN_OK) return 0;
+    return L.total;
+}
+
 size_t sten_tiled_workspace_bytes(int64_t H, int64_t W, int32_t pr, int32_t pc) {
-    if (H < 1 || W < 1 || pr < 1 || pc < 1 || pr > H || pc > W) return 0;
-    std::vector<sten::Tile> tiles;
-    int ns = 0;
-    return sten::plan_layout(H, W, pr, pc, tiles, ns).total;
+    return sten_tiled_workspace_bytes_ex(H, W, pr, pc, 1, STEN_TILED_PACKED);
+}
+
+sten_status sten_tiled_plan_check(int64_t H, int64_t W, int32_t pr, int32_t pc, int32_t ghost, int32_t mode,
+                                  int64_t* info, int32_t n) {
+    using namespace sten;
+    if (info == nullptr || n < 4) return STEN_ERR_ARG;
+    sten_tiled_s plan;
+    Layout L;
+    const sten_status st = make_plan(H, W, pr, pc, ghost, mode, &plan, L);
+    if (st != STEN_OK) return st;
+    // a stand-in base address: pointers are computed, never dereferenced
+    char* base = (char*)(uintptr_t)((uint64_t)1 << 40);
+    build_plan(&plan, L, base);
+    info[0] = (int64_t)plan.tiles.size();
+    info[1] = plan.n_strips;
+    info[2] = plan.n_strips > 0 ? (mode == STEN_TILED_PACKED ? 2 : 1) : 0;
+    info[3] = (int64_t)L.total;
+    return plan_in_bounds(&plan, L, base) ? STEN_OK : STEN_ERR_UNSUPPORTED;
+}
+
+sten_status sten_tiled_create_ex(int64_t H, int64_t W, int32_t pr, int32_t pc, int32_t ghost, int32_t mode,
+                                 void* dev_ws, size_t ws_bytes, sten_tiled_handle* out) {
+    using namespace sten;
+    if (out == nullptr) return STEN_ERR_ARG;
+    *out = nullptr;
+    auto* p = new sten_tiled_s();
+    Layout L;
+    sten_status st = make_plan(H, W, pr, pc, ghost, mode, p, L);
+    if (st == STEN_OK && dev_ws == nullptr) st = STEN_ERR_PTR;
+    if (st == STEN_OK && (uintptr_t)dev_ws % 256 != 0) st = STEN_ERR_ARG;
+    if (st == STEN_OK && ws_bytes < L.total) st = STEN_ERR_WORKSPACE;
+    if (st == STEN_OK && !is_device_ptr(dev_ws)) st = STEN_ERR_PTR;
+    if (st == STEN_OK) {
+        build_plan(p, L, (char*)dev_ws);
+        if (!plan_in_bounds(p, L, (const char*)dev_ws)) st = STEN_ERR_UNSUPPORTED;
+    }
+    if (st == STEN_OK) {
+        hipError_t e = hipEventCreateWithFlags(&p->ev_compute, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_comm, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            if (p->ev_compute) (void)hipEventDestroy(p->ev_compute);
+            st = hip_fail(e);
+        }
+    }
+    if (st != STEN_OK) {
+        delete p;
+        return st;
+    }
+    *out = p;
+    return STEN_OK;
 }
 
 sten_status sten_tiled_create(int64_t H, int64_t W, int32_t pr, int32_t pc, void* dev_ws, size_t ws_bytes,
                               sten_tiled_handle* out) {
-    using namespace sten;
-    if (out == nullptr) return STEN_ERR_ARG;
-    *out = nullptr;
-    if (H < 1 || W < 1 || pr < 1 || pc < 1 || pr > H || pc > W) return STEN_ERR_ARG;
-    if (H > INT32_MAX / 2 || W > INT32_MAX / 2) return STEN_ERR_ARG;
-    if (dev_ws == nullptr) return STEN_ERR_PTR;
-    if ((uintptr_t)dev_ws % 256 != 0) return STEN_ERR_ARG;
-    auto* p = new sten_tiled_s();
-    p->H = H;
-    p->W = W;
-    p->pr = pr;
-    p->pc = pc;
-    int nstrips = 0;
-    Layout L = plan_layout(H, W, pr, pc, p->tiles, nstrips);
-    if (ws_bytes < L.total) {
-        delete p;
-        return STEN_ERR_WORKSPACE;
-    }
-    if (!is_device_ptr(dev_ws)) {
-        delete p;
-        return STEN_ERR_PTR;
-    }
-    char* base = (char*)dev_ws;
-    for (size_t t = 0; t < p->tiles.size(); ++t) {
-        Tile& T = p->tiles[t];
-        const View v = tile_view(T, H, W);
-        for (int k = 0; k < 2; ++k) {
-            // shift the buffer so that the view start lands on a 16-byte boundary
-            double* b = (double*)(base + L.buf_off[k][t]);
-            const int64_t mis = v.off % 2;
-            T.buf[k] = b + (mis ? 1 : 0);
-        }
-        for (int e = 0; e < 4; ++e) T.send[e] = T.nb[e] >= 0 ? (double*)(base + L.send_off[e][t]) : nullptr;
-    }
-    // strip tables: pack (owned boundary -> own send buffer), unpack (neighbour's send -> own ghost)
-    for (int k = 0; k < 2; ++k) {
-        for (const Tile& T : p->tiles) {
-            const double* own = T.buf[k] + T.ldt + 1;  // owned (0, 0)
-            for (int e = 0; e < 4; ++e) {
-                if (T.nb[e] < 0) continue;
-                Strip s{};
-                if (e == 0) s = Strip{own, T.send[e], 1, 1, T.w, 0};
-                if (e == 1) s = Strip{own + (int64_t)(T.h - 1) * T.ldt, T.send[e], 1, 1, T.w, 0};
-                if (e == 2) s = Strip{own, T.send[e], T.ldt, 1, T.h, 0};
-                if (e == 3) s = Strip{own + (T.w - 1), T.send[e], T.ldt, 1, T.h, 0};
-                p->h_pack[k].push_back(s);
-                p->max_strip = std::max(p->max_strip, s.n);
-            }
-        }
-        for (const Tile& T : p->tiles) {
-            double* gb = T.buf[k];  // ghost frame: row 0, row h+1, col 0, col w+1
-            for (int e = 0; e < 4; ++e) {
-                if (T.nb[e] < 0) continue;
-                const Tile& N = p->tiles[T.nb[e]];
-                const int opp = e ^ 1;  // north <-> south, west <-> east
-                Strip s{};
-                if (e == 0) s = Strip{N.send[opp], gb + 1, 1, 1, T.w, 0};
-                if (e == 1) s = Strip{N.send[opp], gb + (int64_t)(T.h + 1) * T.ldt + 1, 1, 1, T.w, 0};
-                if (e == 2) s = Strip{N.send[opp], gb + T.ldt, 1, T.ldt, T.h, 0};
-                if (e == 3) s = Strip{N.send[opp], gb + T.ldt + (T.w + 1), 1, T.ldt, T.h, 0};
-                p->h_unpack[k].push_back(s);
-            }
-        }
-    }
-    p->n_pack = (int)p->h_pack[0].size();
-    p->n_unpack = (int)p->h_unpack[0].size();
-    Strip* tables = (Strip*)(base + L.tables_off);
-    const int n = std::max(nstrips, 1);
-    p->d_pack[0] = tables;
-    p->d_pack[1] = tables + n;
-    p->d_unpack[0] = tables + 2 * n;
-    p->d_unpack[1] = tables + 3 * n;
-    hipError_t e = hipEventCreateWithFlags(&p->ev_compute, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_comm, hipEventDisableTiming);
-    if (e != hipSuccess) {
-        if (p->ev_compute) (void)hipEventDestroy(p->ev_compute);
-        delete p;
-        return hip_fail(e);
-    }
-    *out = p;
-    return STEN_OK;
+    return sten_tiled_create_ex(H, W, pr, pc, 1, STEN_TILED_PACKED, dev_ws, ws_bytes, out);
 }
 
 sten_status sten_tiled_scatter(sten_tiled_handle p, const double* u, int64_t ld, hipStream_t stream) {
@@ -303,11 +497,13 @@ sten_status sten_tiled_scatter(sten_tiled_handle p, const double* u, int64_t ld,
         sten_status st = upload_tables(p, stream);
         if (st != STEN_OK) return st;
     }
+    const int g = p->g;
     for (const Tile& T : p->tiles) {
         const int64_t total = (int64_t)T.h * T.w;
         const uint32_t blocks = (uint32_t)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 4096));
-        block_copy_kernel<<<blocks, 256, 0, stream>>>(u + (int64_t)T.r0 * ld + T.c0, ld, T.buf[0] + T.ldt + 1,
-                                                      T.buf[1] + T.ldt + 1, T.ldt, T.h, T.w);
+        block_copy_kernel<<<blocks, 256, 0, stream>>>(u + (int64_t)T.r0 * ld + T.c0, ld,
+                                                      T.buf[0] + (int64_t)g * T.ldt + g,
+                                                      T.buf[1] + (int64_t)g * T.ldt + g, T.ldt, T.h, T.w);
     }
     p->cur = 0;
     ++p->local_epoch[0];
@@ -321,10 +517,11 @@ sten_status sten_tiled_gather(sten_tiled_handle p, double* u, int64_t ld, hipStr
     if (ld < p->W) return STEN_ERR_ARG;
     if (u == nullptr) return STEN_ERR_PTR;
     if (!is_device_ptr(u)) return STEN_ERR_PTR;
+    const int g = p->g;
     for (const Tile& T : p->tiles) {
         const int64_t total = (int64_t)T.h * T.w;
         const uint32_t blocks = (uint32_t)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 4096));
-        block_copy_kernel<<<blocks, 256, 0, stream>>>(T.buf[p->cur] + T.ldt + 1, T.ldt,
+        block_copy_kernel<<<blocks, 256, 0, stream>>>(T.buf[p->cur] + (int64_t)g * T.ldt + g, T.ldt,
                                                       u + (int64_t)T.r0 * ld + T.c0, nullptr, ld, T.h, T.w);
     }
     return check_launch();
@@ -346,16 +543,15 @@ sten_status sten_tiled_run(sten_tiled_handle p, int32_t T, double c, hipStream_t
         sten_status st = upload_tables(p, compute);
         if (st != STEN_OK) return st;
     }
-    for (int32_t k = 0; k < T; ++k) {
+    if (T == 0) return STEN_OK;
+    // chunks of at most g sweeps between exchanges, split as evenly as the chunk count allows
+    const int chunks = (T + p->g - 1) / p->g;
+    const int base = T / chunks, extra = T % chunks;
+    for (int k = 0; k < chunks; ++k) {
         const int src = p->cur, dst = 1 - p->cur;
         sten_status st = exchange(p, src, compute, comm);
         if (st != STEN_OK) return st;
-        for (const Tile& t : p->tiles) {
-            const View v = tile_view(t, p->H, p->W);
-            if (v.vh < 3 || v.vw < 3) continue;
-            launch_sweep_f64_internal(t.buf[src] + v.off, t.buf[dst] + v.off, v.vh, v.vw, t.ldt, c, compute);
-            ++p->n_sweep_launches;
-        }
+        sweep_tiles(p, src, base + (k < extra ? 1 : 0), c, compute);
         ++p->local_epoch[dst];
         p->cur = dst;
     }
@@ -368,7 +564,9 @@ sten_status sten_tiled_stats(sten_tiled_handle p, int64_t* stats, int32_t n) {
     stats[1] = p->n_exchanges;
     stats[2] = p->n_skipped;
     stats[3] = p->n_sweep_launches;
-    stats[4] = p->n_pack;
+    stats[4] = p->n_strips;
+    if (n >= 6) stats[5] = p->g;
+    if (n >= 7) stats[6] = p->mode;
     return STEN_OK;
 }
 

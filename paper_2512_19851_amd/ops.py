@@ -310,25 +310,35 @@ class BatchPlan:
 # ---------------------------------------------------------------------------
 
 class TiledGrid:
-    """An H x W FP64 grid split into pr x pc tiles with depth-1 ghosts, on one GPU.
+    """An H x W FP64 grid split into pr x pc tiles with ghost frames of depth `ghost`, on one GPU.
 
     t = TiledGrid(H, W, pr, pc); t.scatter(u); t.run(T, c); u2 = t.gather()
+    `ghost` (1..12) is the number of sweeps a tile runs between two ghost exchanges.
+    `exchange` is "packed" (pack and unpack kernels through send buffers) or "direct" (one copy kernel
+    from each neighbour's boundary block into the ghost frame).
     `comm_stream` (optional) carries the ghost exchanges; sweeps go on the current stream.
     """
 
-    def __init__(self, H: int, W: int, pr: int, pc: int, device=None, comm_stream=None):
+    MODES = {"packed": 0, "direct": 1}
+
+    def __init__(self, H: int, W: int, pr: int, pc: int, device=None, comm_stream=None, ghost: int = 1,
+                 exchange: str = "packed"):
         import ctypes
 
         lib = _lib.load()
-        self.H, self.W, self.pr, self.pc = int(H), int(W), int(pr), int(pc)
-        nbytes = int(lib.sten_tiled_workspace_bytes(self.H, self.W, self.pr, self.pc))
+        if exchange not in self.MODES:
+            raise ValueError(f"exchange must be one of {sorted(self.MODES)}")
+        self.H, self.W, self.pr, self.pc, self.ghost = int(H), int(W), int(pr), int(pc), int(ghost)
+        self.mode = self.MODES[exchange]
+        nbytes = int(lib.sten_tiled_workspace_bytes_ex(self.H, self.W, self.pr, self.pc, self.ghost, self.mode))
         if nbytes == 0:
             raise ValueError("invalid tiling")
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device or torch.device("cuda"))
         self.comm_stream = comm_stream
         self._h = ctypes.c_void_p()
-        _lib.check("sten_tiled_create", lib.sten_tiled_create(self.H, self.W, self.pr, self.pc, self.ws.data_ptr(),
-                                                              nbytes, ctypes.byref(self._h)))
+        _lib.check("sten_tiled_create_ex",
+                   lib.sten_tiled_create_ex(self.H, self.W, self.pr, self.pc, self.ghost, self.mode,
+                                            self.ws.data_ptr(), nbytes, ctypes.byref(self._h)))
 
     def _comm(self) -> int:
         return _stream_ptr(self.comm_stream) if self.comm_stream is not None else _stream_ptr()
@@ -355,9 +365,9 @@ class TiledGrid:
     def stats(self) -> dict:
         import ctypes
 
-        buf = (ctypes.c_int64 * 5)()
-        _lib.call("sten_tiled_stats", self._h, buf, 5)
-        return dict(zip(["tiles", "exchanges", "skipped", "sweep_launches", "strips"], list(buf)))
+        buf = (ctypes.c_int64 * 7)()
+        _lib.call("sten_tiled_stats", self._h, buf, 7)
+        return dict(zip(["tiles", "exchanges", "skipped", "sweep_launches", "strips", "ghost", "mode"], list(buf)))
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:

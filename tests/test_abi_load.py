@@ -113,6 +113,71 @@ def test_tiled_workspace_query(lib):
     assert many > one  # ghost frames and send buffers grow with the tile count
 
 
+def test_tiled_ghost_workspace_query(lib):
+    """Deeper ghost frames need more space; a tile thinner than the ghost depth across a shared edge is refused."""
+    ws = lib.sten_tiled_workspace_bytes_ex
+    g1 = ws(64, 64, 2, 2, 1, 0)
+    assert g1 == lib.sten_tiled_workspace_bytes(64, 64, 2, 2)
+    assert ws(64, 64, 2, 2, 8, 0) > g1
+    assert 0 < ws(64, 64, 2, 2, 8, 1) < ws(64, 64, 2, 2, 8, 0)  # direct mode has no send buffers
+    assert ws(64, 64, 2, 2, 1, 2) == 0                           # unknown mode
+    assert ws(64, 64, 2, 2, 0, 0) == 0
+    assert ws(64, 64, 2, 2, 13, 0) == 0
+    assert ws(20, 64, 4, 1, 5, 0) > 0   # tiles 5 rows tall
+    assert ws(20, 64, 4, 1, 6, 0) == 0  # thinner than the ghost depth
+    assert ws(3, 64, 1, 4, 12, 1) > 0   # one tile row: row count is free
+
+
+def _plan(lib, H, W, pr, pc, g, mode=0):
+    import ctypes
+
+    info = (ctypes.c_int64 * 4)()
+    st = lib.sten_tiled_plan_check(H, W, pr, pc, g, mode, info, 4)
+    return st, list(info)
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["packed", "direct"])
+@pytest.mark.parametrize("g", [1, 2, 3, 7, 12])
+def test_tiled_plan_in_bounds(lib, g, mode):
+    """Every exchange copy, owned block and sweep view of a plan lies inside its buffer (host check, no
+    device), over square, ragged, single-row and single-column tilings."""
+    shapes = [(5, 7), (64, 64), (130, 513), (257, 1031), (100, 300), (3, 600), (600, 3), (4096, 4096),
+              (97, 143), (50, 50)]
+    tilings = [(1, 1), (2, 2), (3, 5), (1, 6), (7, 1), (4, 4), (2, 3)]
+    checked = 0
+    for H, W in shapes:
+        for pr, pc in tilings:
+            valid = lib.sten_tiled_workspace_bytes_ex(H, W, pr, pc, g, mode) > 0
+            st, info = _plan(lib, H, W, pr, pc, g, mode)
+            if not valid:
+                assert st == -1, (H, W, pr, pc, g)
+                continue
+            assert st == 0, (H, W, pr, pc, g)
+            tiles, msgs, launches, nbytes = info
+            assert tiles == pr * pc
+            # one message per edge shared by two tiles in each direction, and for g > 1 one per
+            # diagonal pair of tiles in each direction
+            edges = 2 * (pr * (pc - 1) + pc * (pr - 1))
+            corners = 4 * (pr - 1) * (pc - 1) if g > 1 else 0
+            assert msgs == edges + corners
+            assert launches == (0 if msgs == 0 else (2 if mode == 0 else 1))
+            assert nbytes == lib.sten_tiled_workspace_bytes_ex(H, W, pr, pc, g, mode)
+            checked += 1
+    assert checked > 20
+
+
+def test_tiled_plan_rejects(lib):
+    import ctypes
+
+    assert _plan(lib, 64, 64, 65, 1, 1)[0] == -1
+    assert _plan(lib, 64, 64, 2, 2, 0)[0] == -1
+    assert _plan(lib, 8, 64, 2, 1, 5)[0] == -1
+    assert _plan(lib, 64, 64, 2, 2, 2, mode=5)[0] == -1
+    assert lib.sten_tiled_plan_check(64, 64, 2, 2, 2, 0, None, 4) == -1
+    info = (ctypes.c_int64 * 3)()
+    assert lib.sten_tiled_plan_check(64, 64, 2, 2, 2, 0, info, 3) == -1
+
+
 def test_expr_run_rejects_before_any_hip_call(lib):
     """Program syntax, load extents and aliasing are checked on the host (fake pointers, no device)."""
     import ctypes
