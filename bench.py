@@ -39,7 +39,8 @@ METRIC = "hot-path GB/s or FLOP/s and % roofline, plain FP64 vs mixed/batched at
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_f64_4096_traffic.json")
 SWEEP_SRC = os.path.join(ROOT, "paper_2512_19851_amd", "csrc", "sweep.hip")
 TB_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_stream_f64_4096_traffic.json")
-TB_SRC = os.path.join(ROOT, "paper_2512_19851_amd", "csrc", "temporal.hip")
+TB_SRC = [os.path.join(ROOT, "paper_2512_19851_amd", "csrc", "temporal.hip"),
+          os.path.join(ROOT, "paper_2512_19851_amd", "csrc", "stream_common.hpp")]
 TB_LEVELS = 10  # sweeps per launch of the built-in schedule
 PREWARM_S = 0.25  # seconds of untimed steps before the timed region
 
@@ -48,19 +49,23 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def source_sha(path: str) -> str:
-    """Hash of the kernel's code: the region between the BEGIN/END KERNEL SOURCE markers with `//`
-    comments, trailing blanks and blank lines removed, so that only a change of code invalidates
-    counters taken on it."""
-    with open(path, encoding="utf-8") as f:
-        text = f.read()
-    a = text.find("BEGIN KERNEL SOURCE")
-    b = text.find("END KERNEL SOURCE")
-    if a >= 0 and b > a:
-        text = text[a:b]
-    lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines()]
-    code = "\n".join(ln for ln in lines if ln.strip())
-    return hashlib.sha256(code.encode()).hexdigest()[:16]
+def source_sha(paths) -> str:
+    """Hash of a kernel's code: in each file (one path or a list), the region between the BEGIN/END
+    KERNEL SOURCE markers with `//` comments, trailing blanks and blank lines removed, so that only a
+    change of code invalidates counters taken on it."""
+    if isinstance(paths, str):
+        paths = [paths]
+    parts = []
+    for path in paths:
+        with open(os.path.join(ROOT, path) if not os.path.isabs(path) else path, encoding="utf-8") as f:
+            text = f.read()
+        a = text.find("BEGIN KERNEL SOURCE")
+        b = text.find("END KERNEL SOURCE")
+        if a >= 0 and b > a:
+            text = text[a:b]
+        lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines()]
+        parts.append("\n".join(ln for ln in lines if ln.strip()))
+    return hashlib.sha256("\n".join(parts).encode()).hexdigest()[:16]
 
 
 def load_traffic(path: str, src: str):
@@ -449,41 +454,53 @@ def bench_frontend(ops, args) -> dict:
 
 def bench_cavity(args, n: int = 16384, nit: int = 50, steps: int = 2) -> dict:
     """The paper's second application (Section V): lid-driven cavity flow, 16k x 16k per GPU, written
-    as slice assignments on the frontend; most nodes run as generated kernels, the u and v updates fused."""
+    as slice assignments on the frontend; most nodes run as generated kernels, the u and v updates fused.
+    Two pressure solves: the blocked library call (default) and one frontend node per iteration."""
     import torch
 
     from paper_2512_19851_amd import frontend
     from paper_2512_19851_amd.cavity import CavityFlow
 
-    log(f"[bench] cavity flow {n}x{n}, {nit} pressure iterations per step")
-    ctx = frontend.Context(max_depth=64)
-    flow = CavityFlow(ctx, n, n, nit=nit)
-    t0 = time.perf_counter()
-    flow.run(1)  # warm-up: compiles the generated kernels (hiprtc) once per process
-    ctx.sync()
-    warm = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    flow.run(steps)
-    ctx.sync()
-    sec = (time.perf_counter() - t0) / steps
     interior = (n - 2) ** 2
     # algorithmic bytes per step: source (read u, v; write b), nit pressure iterations (read p, b;
     # write p), velocities (read u, v, p; write u, v); walls are O(n)
     step_bytes = interior * (24 + 24 * nit + 40)
-    u, v, p = flow.fields()
-    finite = bool(torch.isfinite(u).all() and torch.isfinite(v).all() and torch.isfinite(p).all())
-    del flow, ctx, u, v, p
-    torch.cuda.empty_cache()
-    return {
+    res = {
         "workload": f"{n}x{n} FP64, rest start, lid u = 1, nu = 0.1, dt = 0.001, {nit} pressure iterations per "
                     f"step, {steps} timed steps after one warm-up step",
-        "ms_per_step": round(sec * 1e3, 2),
-        "effective_GBps": round(step_bytes / sec / 1e9, 1),
         "algorithmic_bytes_per_step": step_bytes,
-        "warmup_step_s_incl_compile": round(warm, 2),
-        "fields_finite": finite,
-        "parity": "bit-identical to the NumPy oracle on 5x5 ... 257x513 (tests/test_gpu_cavity.py)",
+        "parity": "bit-identical to the NumPy oracle on 3x130 ... 257x513, both pressure solves "
+                  "(tests/test_gpu_cavity.py, tests/test_gpu_pressure.py)",
     }
+    fields = {}
+    for blocked in (True, False):
+        log(f"[bench] cavity flow {n}x{n}, {nit} pressure iterations per step, blocked pressure {blocked}")
+        ctx = frontend.Context(max_depth=64)
+        flow = CavityFlow(ctx, n, n, nit=nit, blocked_pressure=blocked)
+        t0 = time.perf_counter()
+        flow.run(1)  # warm-up: compiles the generated kernels (hiprtc) once per process
+        ctx.sync()
+        warm = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        flow.run(steps)
+        ctx.sync()
+        sec = (time.perf_counter() - t0) / steps
+        u, v, p = flow.fields()
+        fields[blocked] = (u.clone(), v.clone(), p.clone())
+        finite = bool(torch.isfinite(u).all() and torch.isfinite(v).all() and torch.isfinite(p).all())
+        res["blocked_pressure" if blocked else "per_node_pressure"] = {
+            "ms_per_step": round(sec * 1e3, 2),
+            "effective_GBps": round(step_bytes / sec / 1e9, 1),
+            "warmup_step_s_incl_compile": round(warm, 2),
+            "fields_finite": finite,
+        }
+        del flow, ctx, u, v, p
+    res["blocked_bit_identical_to_per_node"] = all(torch.equal(a, b) for a, b in zip(fields[True], fields[False]))
+    res["speedup_blocked_vs_per_node"] = round(res["per_node_pressure"]["ms_per_step"] /
+                                               res["blocked_pressure"]["ms_per_step"], 2)
+    del fields
+    torch.cuda.empty_cache()
+    return res
 
 
 def bench_adjoint(T: int, args) -> dict:

@@ -152,6 +152,37 @@ sten_status sten_tune_schedule(int32_t levels);
 sten_status sten_tune_sweep_rows(int32_t rows);
 
 /* ------------------------------------------------------------------------ */
+/* Cavity flow: blocked pressure iterations (Section V's second benchmark)  */
+/* ------------------------------------------------------------------------ */
+/*
+ * nit Jacobi iterations of the lid-driven cavity flow's pressure equation,
+ * each followed by its wall conditions, starting from p0 with source term b
+ * (H x W FP64, row stride ld, device memory; the result goes to out). One
+ * iteration maps p to q:
+ *   q[i,j] = (cw * (p[i,j+1] + p[i,j-1]) + cn * (p[i+1,j] + p[i-1,j])) - cb * b[i,j]
+ *            on rows 1..H-2, columns 1..W-2, evaluated in this order;
+ *   q[i,W-1] = q[i,W-2], q[i,0] = q[i,1] on rows 1..H-2 (dp/dx = 0);
+ *   q[0,:] = q[1,:] (dp/dy = 0, corners included); q[H-1,:] = 0 (the lid).
+ * Up to `levels` iterations (1..8; 0 = 8) run per pass over HBM, the nit
+ * iterations split as evenly as ceil(nit / levels) passes allow. The result
+ * is bit-identical to applying the iteration nit times.
+ * work: a second H x W buffer, needed when nit > levels (else may be NULL).
+ * Errors: STEN_ERR_ARG (negative sizes or nit, ld < W, levels > 8);
+ * STEN_ERR_PTR (NULL or non-device pointers); STEN_ERR_ALIAS (out or work
+ * overlapping p0, b or each other); STEN_ERR_UNSUPPORTED for layouts the
+ * blocked kernel does not take: H < 3, W < 128, W or ld odd, pointers not
+ * 16-byte aligned, rows of 2^27 elements or more (the caller then runs the
+ * iterations one at a time). nit = 0 copies p0 to out.
+ */
+sten_status sten_cavity_pressure_f64(const double* p0, const double* b, double* out, double* work, int64_t H,
+                                     int64_t W, int64_t ld, int32_t nit, double cw, double cn, double cb,
+                                     int32_t levels, hipStream_t stream);
+
+/* Tuning hook of the blocked pressure kernel: rows per band (1..65536; 0
+ * restores the built-in choice). Results unchanged. STEN_ERR_ARG otherwise. */
+sten_status sten_tune_pressure(int32_t band);
+
+/* ------------------------------------------------------------------------ */
 /* Reduced-precision form: hi/lo encoding (extension; not in the paper)     */
 /* ------------------------------------------------------------------------ */
 /*

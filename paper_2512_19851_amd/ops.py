@@ -133,6 +133,40 @@ def set_sweep_rows(rows: int) -> None:
 # hi/lo reduced-precision form
 # ---------------------------------------------------------------------------
 
+def cavity_pressure(p0: torch.Tensor, b: torch.Tensor, nit: int, cw: float, cn: float, cb: float, levels: int = 0,
+                    out: torch.Tensor | None = None, work: torch.Tensor | None = None,
+                    stream=None) -> torch.Tensor:
+    """nit pressure iterations of the lid-driven cavity flow (interior update, then the wall conditions), up to
+    `levels` (1..8, 0 = 8) per pass over HBM; bit-identical to one iteration at a time. FP64 grids of one
+    shape and stride. Raises StenError with name STEN_ERR_UNSUPPORTED for layouts the blocked kernel does not
+    take (fewer than 3 rows or 128 columns, odd width or stride, unaligned data)."""
+    for t, name in ((p0, "p0"), (b, "b")):
+        _check_grid(t, torch.float64, name)
+    if b.shape != p0.shape or (p0.shape[0] > 1 and b.stride() != p0.stride()):
+        raise ValueError("b must match p0's shape and strides")
+    H, W = p0.shape
+    if out is None:
+        out = torch.empty_strided(p0.shape, p0.stride(), dtype=p0.dtype, device=p0.device)
+    lev = levels if levels > 0 else 8
+    if work is None and nit > lev:
+        work = torch.empty_strided(p0.shape, p0.stride(), dtype=p0.dtype, device=p0.device)
+    for t, name in ((out, "out"), (work, "work")):
+        if t is None:
+            continue
+        _check_grid(t, torch.float64, name)
+        if t.shape != p0.shape or (H > 1 and t.stride() != p0.stride()):
+            raise ValueError(f"{name} must match p0's shape and strides")
+    _lib.call("sten_cavity_pressure_f64", p0.data_ptr(), b.data_ptr(), out.data_ptr(),
+              work.data_ptr() if work is not None else None, H, W, _ld(p0), int(nit), float(cw), float(cn),
+              float(cb), int(levels), _stream_ptr(stream))
+    return out
+
+
+def set_pressure_band(band: int) -> None:
+    """Rows per band of the blocked pressure kernel (0: built-in). Results are unchanged."""
+    _lib.call("sten_tune_pressure", int(band))
+
+
 class HiLoGrid:
     """An encoded grid in a device byte buffer: FP32 hi plane + int16 q plane."""
 

@@ -178,6 +178,27 @@ def test_tiled_plan_rejects(lib):
     assert lib.sten_tiled_plan_check(64, 64, 2, 2, 2, 0, info, 3) == -1
 
 
+def test_cavity_pressure_rejects_before_any_hip_call(lib):
+    """Sizes, pointers, aliasing and the blocked kernel's layout are checked on the host (fake pointers)."""
+    f = lib.sten_cavity_pressure_f64
+    A, B, O, K = 1 << 30, 2 << 30, 3 << 30, 4 << 30  # disjoint fake addresses, 16-byte aligned
+    assert f(A, B, O, K, -1, 128, 128, 3, 0.2, 0.3, 0.1, 0, None) == -1   # H < 0
+    assert f(A, B, O, K, 8, 128, 127, 3, 0.2, 0.3, 0.1, 0, None) == -1    # ld < W
+    assert f(A, B, O, K, 8, 128, 128, -1, 0.2, 0.3, 0.1, 0, None) == -1   # nit < 0
+    assert f(A, B, O, K, 8, 128, 128, 3, 0.2, 0.3, 0.1, 9, None) == -1    # levels > 8
+    assert f(A, B, O, K, 0, 128, 128, 3, 0.2, 0.3, 0.1, 0, None) == 0     # empty: no-op
+    assert f(None, B, O, K, 8, 128, 128, 3, 0.2, 0.3, 0.1, 0, None) == -3
+    assert f(A, B, O, None, 8, 128, 128, 9, 0.2, 0.3, 0.1, 0, None) == -3  # two passes need work
+    assert f(A, B, A + 64, K, 8, 128, 128, 3, 0.2, 0.3, 0.1, 0, None) == -2  # out overlaps p0
+    assert f(A, B, O, B, 8, 128, 128, 9, 0.2, 0.3, 0.1, 0, None) == -2       # work overlaps b
+    assert f(A, B, O, K, 8, 126, 128, 3, 0.2, 0.3, 0.1, 0, None) == -6      # W < 128
+    assert f(A, B, O, K, 8, 129, 130, 3, 0.2, 0.3, 0.1, 0, None) == -6      # odd W
+    assert f(A, B, O, K, 2, 128, 128, 3, 0.2, 0.3, 0.1, 0, None) == -6      # H < 3
+    assert f(A + 8, B, O, K, 8, 128, 128, 3, 0.2, 0.3, 0.1, 0, None) == -6  # unaligned
+    assert lib.sten_tune_pressure(-1) == -1
+    assert lib.sten_tune_pressure(0) == 0
+
+
 def test_expr_run_rejects_before_any_hip_call(lib):
     """Program syntax, load extents and aliasing are checked on the host (fake pointers, no device)."""
     import ctypes

@@ -26,3 +26,22 @@ def test_cavity_bit_exact(shape, nit, nt):
     assert np.array_equal(v, vo)
     assert np.array_equal(p, po)
     assert ctx.stats["fused_nodes"] >= 2 * nt  # u and v updates fused every step
+
+
+@pytest.mark.parametrize("blocked", [True, False], ids=["blocked", "per_node"])
+@pytest.mark.parametrize("shape,nit,nt", [((130, 256), 50, 3), ((64, 128), 7, 4), ((3, 130), 5, 2)],
+                         ids=["130x256", "64x128", "3x130"])
+def test_cavity_blocked_pressure_bit_exact(shape, nit, nt, blocked):
+    """The pressure iterations as one blocked call per step give the per-node program's bits."""
+    device()
+    H, W = shape
+    say(f"cavity {shape} nit={nit} nt={nt} blocked={blocked}")
+    ctx = fe.Context(max_depth=64)
+    flow = CavityFlow(ctx, H, W, nit=nit, blocked_pressure=blocked)
+    assert flow.blocked_pressure == blocked
+    flow.run(nt)
+    u, v, p = (to_host(x) for x in flow.fields())
+    uo, vo, po = oc.run(nt, oc.CavityParams(H, W, nit=nit))
+    assert np.array_equal(u, uo)
+    assert np.array_equal(v, vo)
+    assert np.array_equal(p, po)

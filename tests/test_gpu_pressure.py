@@ -1,0 +1,118 @@
+"""Blocked pressure iterations of the cavity flow against the oracle, via the C ABI.
+
+Several pressure iterations per pass over HBM (the walls applied at every
+level inside the kernel) must give the bits of the oracle's one-at-a-time
+iteration, for every level count, band height, ragged shape and both walk
+directions of the bands.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import cavity as oc
+from tests.gpu_util import device, say, to_dev, to_host
+from workloads import normal_grid
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ops():
+    device()
+    from paper_2512_19851_amd import ops
+
+    yield ops
+    ops.set_pressure_band(0)
+
+
+def _want(p0, b, prm, nit):
+    p = p0.copy()
+    for _ in range(nit):
+        p = oc.pressure_iteration(p, b, prm)
+    return p
+
+
+def _inputs(H, W, seed):
+    # unequal spacings, so that the two neighbour weights differ
+    prm = oc.CavityParams(H, W, lx=2.0, ly=1.3)
+    return normal_grid(H, W, seed=seed), normal_grid(H, W, seed=seed + 1), prm
+
+
+SHAPES = [(3, 128), (4, 130), (5, 256), (64, 128), (67, 258), (130, 300), (257, 1030), (40, 2050), (600, 128)]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"{s[0]}x{s[1]}")
+def test_pressure_bit_exact_every_level(ops, shape):
+    H, W = shape
+    p0, b, prm = _inputs(H, W, seed=H + W)
+    dp, db = to_dev(p0), to_dev(b)
+    for nit in (0, 1, 2, 3, 8, 9, 17):
+        want = _want(p0, b, prm, nit)
+        for levels in range(0, 9):
+            say(f"pressure {shape} nit={nit} levels={levels}")
+            got = to_host(ops.cavity_pressure(dp, db, nit, prm.cw, prm.cn, prm.cb, levels=levels))
+            assert np.array_equal(got, want), f"{shape} nit={nit} levels={levels}"
+
+
+@pytest.mark.parametrize("band", [1, 2, 5, 16, 1000])
+def test_pressure_band_heights(ops, band):
+    """Bands of one row (every band's warm-up passes the bottom wall or the lid), ragged last bands, one band
+    for the whole grid; odd bands walk upward."""
+    try:
+        ops.set_pressure_band(band)
+        for H, W in ((37, 128), (130, 260), (11, 512)):
+            p0, b, prm = _inputs(H, W, seed=3 * H + band)
+            dp, db = to_dev(p0), to_dev(b)
+            for nit, levels in ((5, 5), (16, 8), (7, 3), (1, 1)):
+                say(f"pressure band={band} {H}x{W} nit={nit} levels={levels}")
+                got = to_host(ops.cavity_pressure(dp, db, nit, prm.cw, prm.cn, prm.cb, levels=levels))
+                assert np.array_equal(got, _want(p0, b, prm, nit)), (band, H, W, nit, levels)
+    finally:
+        ops.set_pressure_band(0)
+
+
+def test_pressure_fifty_iterations(ops):
+    """The cavity flow's 50 iterations per time step, on a 1024 x 1024 grid."""
+    H = W = 1024
+    p0, b, prm = _inputs(H, W, seed=9)
+    say("pressure 1024x1024 nit=50")
+    got = to_host(ops.cavity_pressure(to_dev(p0), to_dev(b), 50, prm.cw, prm.cn, prm.cb))
+    assert np.array_equal(got, _want(p0, b, prm, 50))
+
+
+def test_pressure_full_size(ops):
+    H = W = 4096
+    p0, b, prm = _inputs(H, W, seed=21)
+    say("pressure 4096x4096 nit=9")
+    got = to_host(ops.cavity_pressure(to_dev(p0), to_dev(b), 9, prm.cw, prm.cn, prm.cb))
+    assert np.array_equal(got, _want(p0, b, prm, 9))
+
+
+def test_pressure_strided_view(ops):
+    """Views with a row stride wider than the grid (the padding is neither read nor written)."""
+    import torch
+
+    H, W = 70, 256
+    p0, b, prm = _inputs(H, W, seed=4)
+    big_p = torch.full((H, W + 64), float("nan"), dtype=torch.float64, device="cuda")
+    big_b = torch.full((H, W + 64), float("nan"), dtype=torch.float64, device="cuda")
+    big_o = torch.full((H, W + 64), 7.0, dtype=torch.float64, device="cuda")
+    big_w = torch.full((H, W + 64), 7.0, dtype=torch.float64, device="cuda")
+    big_p[:, 32:32 + W] = to_dev(p0)
+    big_b[:, 32:32 + W] = to_dev(b)
+    say("pressure strided view")
+    ops.cavity_pressure(big_p[:, 32:32 + W], big_b[:, 32:32 + W], 12, prm.cw, prm.cn, prm.cb, levels=5,
+                        out=big_o[:, 32:32 + W], work=big_w[:, 32:32 + W])
+    got = to_host(big_o)
+    assert np.array_equal(got[:, 32:32 + W], _want(p0, b, prm, 12))
+    assert (got[:, :32] == 7.0).all() and (got[:, 32 + W:] == 7.0).all()
+
+
+def test_pressure_unsupported_layouts(ops):
+    from paper_2512_19851_amd import _lib
+
+    for H, W in ((2, 128), (10, 127), (10, 100)):
+        d = to_dev(np.zeros((H, W)))
+        with pytest.raises(_lib.StenError) as e:
+            ops.cavity_pressure(d, d.clone(), 3, 0.25, 0.25, 0.1)
+        assert e.value.name == "STEN_ERR_UNSUPPORTED"
