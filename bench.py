@@ -41,6 +41,9 @@ SWEEP_SRC = os.path.join(ROOT, "paper_2512_19851_amd", "csrc", "sweep.hip")
 TB_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_stream_f64_4096_traffic.json")
 TB_SRC = [os.path.join(ROOT, "paper_2512_19851_amd", "csrc", "temporal.hip"),
           os.path.join(ROOT, "paper_2512_19851_amd", "csrc", "stream_common.hpp")]
+PRESSURE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pressure_stream_f64_16384_traffic.json")
+PRESSURE_SRC = [os.path.join(ROOT, "paper_2512_19851_amd", "csrc", "pressure.hip"),
+                os.path.join(ROOT, "paper_2512_19851_amd", "csrc", "stream_common.hpp")]
 TB_LEVELS = 10  # sweeps per launch of the built-in schedule
 PREWARM_S = 0.25  # seconds of untimed steps before the timed region
 
@@ -496,11 +499,51 @@ def bench_cavity(args, n: int = 16384, nit: int = 50, steps: int = 2) -> dict:
         }
         del flow, ctx, u, v, p
     res["blocked_bit_identical_to_per_node"] = all(torch.equal(a, b) for a, b in zip(fields[True], fields[False]))
+    passes = bench_pressure_passes(n, 5)
+    traffic = load_traffic(PRESSURE_TRAFFIC_FILE, PRESSURE_SRC) if n == 16384 else None
+    passes["traffic"] = traffic
+    passes["hbm_use_frac"] = (round(traffic / (passes["avg_us_per_call"] * 1e-6) / (HBM_PEAK_GBS * 1e9), 4)
+                              if traffic else None)
+    res["pressure_pass"] = passes
     res["speedup_blocked_vs_per_node"] = round(res["per_node_pressure"]["ms_per_step"] /
                                                res["blocked_pressure"]["ms_per_step"], 2)
     del fields
     torch.cuda.empty_cache()
     return res
+
+
+def bench_pressure_passes(n: int, reps: int, levels: int = 8) -> dict:
+    """`reps` launches of the blocked pressure kernel, each one pass of `levels` cavity pressure iterations
+    on an n x n FP64 grid (N(0,1) p and b, seed 0), timed with HIP events on the launch stream."""
+    import torch
+
+    from oracle.cavity import CavityParams
+    from paper_2512_19851_amd import ops
+    from workloads import normal_grid
+
+    prm = CavityParams(n, n)
+    p0 = torch.from_numpy(normal_grid(n, n, seed=0)).to("cuda:0")
+    b = torch.from_numpy(normal_grid(n, n, seed=1)).to("cuda:0")
+    out = torch.empty_like(p0)
+    for _ in range(3):
+        ops.cavity_pressure(p0, b, levels, prm.cw, prm.cn, prm.cb, levels=levels, out=out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        ops.cavity_pressure(p0, b, levels, prm.cw, prm.cn, prm.cb, levels=levels, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    per_ms = e0.elapsed_time(e1) / reps
+    interior = (n - 2) ** 2
+    return {"mode": "pressure", "grid": [n, n], "levels": levels, "launches": reps,
+            "avg_us_per_call": round(per_ms * 1e3, 2),
+            "note": "a call is the lid fill kernel plus one blocked launch",
+            "algorithmic_bytes_per_launch": 24.0 * interior * levels,
+            "pass_floor_bytes": 24.0 * interior,
+            "pass_floor_frac": round(24.0 * interior / (per_ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
 
 
 def bench_adjoint(T: int, args) -> dict:
@@ -566,12 +609,13 @@ def main() -> int:
     ap.add_argument("--cpu-budget", type=float, default=16.0, help="seconds of CPU oracle work")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extensions", action="store_true")
-    ap.add_argument("--mode", choices=["step", "sweep", "copy", "hilo", "tb", "cavity"], default="step",
+    ap.add_argument("--mode", choices=["step", "sweep", "copy", "hilo", "tb", "cavity", "pressure"], default="step",
                     help="step: the benchmark; sweep: only --kernel-reps sweep launches; "
                          "copy: only --kernel-reps plain grid copies (counter calibration); "
                          "hilo: only --kernel-reps hi/lo sweeps on encoded grids; "
                          "tb: only --kernel-reps temporally blocked launches; "
-                         "cavity: only the cavity-flow extension (--n grid side)")
+                         "cavity: only the cavity-flow extension (--n grid side); "
+                         "pressure: only --kernel-reps blocked passes of 8 cavity pressure iterations (--n)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -590,6 +634,9 @@ def main() -> int:
     torch.cuda.set_device(dev)
     if args.mode == "cavity":
         print(json.dumps({"mode": "cavity", **bench_cavity(args, n=args.n)}), flush=True)
+        return 0
+    if args.mode == "pressure":
+        print(json.dumps(bench_pressure_passes(args.n, args.kernel_reps)), flush=True)
         return 0
     n, T = args.n, args.sweeps
     log(f"[bench] generating {n}x{n} FP64 N(0,1) seed 0")
