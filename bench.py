@@ -438,20 +438,28 @@ def bench_frontend(ops, args) -> dict:
         ops.jacobi5(u, T)
         torch.cuda.synchronize()
         ideal.append(time.perf_counter() - t0)
-    res = {"workload": f"listing program, {n}x{n} FP64 unit ring, {T} iterations", "ideal_ms": round(min(ideal) * 1e3, 2)}
+    res = {"workload": f"listing program, {n}x{n} FP64 unit ring, {T} iterations; per DAG depth the best "
+                       f"of 3 runs (the first loads the kernels a chain plan needs)",
+           "ideal_ms": round(min(ideal) * 1e3, 2)}
     for depth in (1, 10, 100, 1000):
-        ctx = frontend.Context(max_depth=depth)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        u1 = ctx.create_array((n, n))
-        u2 = ctx.create_array((n, n))
-        u1[0, :] = u1[-1, :] = u1[:, 0] = u1[:, -1] = 1
-        u2[0, :] = u2[-1, :] = u2[:, 0] = u2[:, -1] = 1
-        for _ in range(T):
-            u2[1:-1, 1:-1] = 0.25 * (u1[:-2, 1:-1] + u1[2:, 1:-1] + u1[1:-1, :-2] + u1[1:-1, 2:])
-            u1, u2 = u2, u1
-        ctx.sync()
-        res[f"depth_{depth}_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+        best = None
+        for _ in range(3):
+            ctx = frontend.Context(max_depth=depth)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u1 = ctx.create_array((n, n))
+            u2 = ctx.create_array((n, n))
+            u1[0, :] = u1[-1, :] = u1[:, 0] = u1[:, -1] = 1
+            u2[0, :] = u2[-1, :] = u2[:, 0] = u2[:, -1] = 1
+            for _ in range(T):
+                u2[1:-1, 1:-1] = 0.25 * (u1[:-2, 1:-1] + u1[2:, 1:-1] + u1[1:-1, :-2] + u1[1:-1, 2:])
+                u1, u2 = u2, u1
+            ctx.sync()
+            sec = time.perf_counter() - t0
+            best = sec if best is None else min(best, sec)
+        res[f"depth_{depth}_ms"] = round(best * 1e3, 2)
+        res[f"depth_{depth}_chained_nodes"] = ctx.stats["chained_nodes"]
+        del ctx, u1, u2
     return res
 
 

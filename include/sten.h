@@ -98,6 +98,20 @@ sten_status sten_sweep_f64(const double* src, double* dst, int64_t H, int64_t W,
 sten_status sten_sweep_f32(const float* src, float* dst, int64_t H, int64_t W, int64_t ld, float c,
                            hipStream_t stream);
 
+/* The listing's loop on two arrays (Section III-A): m sweeps with coefficient c
+ * ping-ponging between a and b, starting from a (sweep 1 reads a and writes
+ * b's interior, sweep k reads the array sweep k-1 wrote). Afterwards the array
+ * sweep m wrote holds iterate m and the other holds iterate m-1, exactly as
+ * after m single sweeps, PROVIDED the rings of a and b hold the same values (a
+ * sweep never writes a ring, so with equal rings every level of a blocked
+ * launch sees the ring the single sweep would). The first m-1 sweeps run as
+ * blocked launches of up to the plain schedule's levels (sten_tune_schedule),
+ * the last as one sweep. a, b: H x W FP64, row stride ld, device memory, not
+ * overlapping (STEN_ERR_ALIAS). m = 0 or an empty interior: no-op. Rows of
+ * 2^27 elements or more, odd ld or unaligned data run as single sweeps. */
+sten_status sten_sweep_chain_f64(double* a, double* b, int64_t H, int64_t W, int64_t ld, int32_t m, double c,
+                                 hipStream_t stream);
+
 /*
  * Temporal blocking (the same method, a different schedule): each launch
  * applies up to `levels` sweeps while reading and writing the grid once, so one

@@ -105,6 +105,7 @@ class CavityFlow:
             self.ctx.flush()  # b's node goes to the stream before the call that reads it
             ops.cavity_pressure(self.p.data, self.b.data, self.nit, self.cw, self.cn, self.cb,
                                 out=self.p_next.data, work=self._p_work)
+            self.ctx.invalidate(self.p_next)  # written outside the frontend
             self.p, self.p_next = self.p_next, self.p
         else:
             for _ in range(self.nit):

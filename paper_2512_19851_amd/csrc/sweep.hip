@@ -24,6 +24,8 @@
 
 namespace sten {
 
+void launch_levels_f64(const double* in, double* out, int H, int W, int64_t ld, double c, int levels,
+                       hipStream_t s);
 sten_status run_tb_f64(const double* u0, double* out, double* work, int64_t H, int64_t W, int64_t ld, int32_t T,
                        double c, int32_t levels, hipStream_t stream);
 sten_status run_tb_f32(const float* u0, float* out, float* work, int64_t H, int64_t W, int64_t ld, int32_t T,
@@ -307,6 +309,52 @@ sten_status run_sweep_once(const T* src, T* dst, int64_t H, int64_t W, int64_t l
 
 }  // namespace
 
+void launch_sweep_f64_internal(const double* in, double* out, int H, int W, int64_t ld, double c, hipStream_t s);
+
+// m sweeps ping-ponging between a and b from a (the listing's loop on two
+// arrays with equal rings): the first m-1 as blocked launches that end in the
+// array iterate m-1 belongs to, then one plain sweep into the other array.
+sten_status run_chain_f64(double* a, double* b, int64_t H, int64_t W, int64_t ld, int32_t m, double c,
+                          hipStream_t stream) {
+    if (H < 0 || W < 0 || (H > 0 && ld < W) || m < 0 || H > INT32_MAX / 2 || W > INT32_MAX / 2)
+        return STEN_ERR_ARG;
+    if (m == 0 || H < 3 || W < 3) return STEN_OK;
+    if (a == nullptr || b == nullptr) return STEN_ERR_PTR;
+    const size_t span = span_bytes(H, W, ld, sizeof(double));
+    if (overlaps(a, span, b, span)) return STEN_ERR_ALIAS;
+    if (!is_device_ptr(a) || !is_device_ptr(b)) return STEN_ERR_PTR;
+    const int h = (int)H, w = (int)W;
+    const int L = g_schedule == 0 ? default_levels<double>() : g_schedule;
+    const bool blocked = L > 1 && (((uintptr_t)a | (uintptr_t)b) % 16) == 0 && ld % 2 == 0 &&
+                         W * (int64_t)sizeof(double) < ((int64_t)1 << 30);
+    const int n = m - 1;  // sweeps before the last one
+    const double* src = a;
+    if (blocked && n >= 2) {
+        // k launches; launch j writes b for odd j, a for even j, and the k-th must write the array
+        // that holds iterate n (b when n is odd), so k and n have the same parity
+        int k = (n + L - 1) / L;
+        if (k % 2 != n % 2) ++k;
+        const int base = n / k, extra = n % k;
+        for (int j = 1; j <= k; ++j) {
+            double* dst = (j % 2) ? b : a;
+            const int lev = base + (j <= extra ? 1 : 0);
+            if (lev == 1)
+                launch_sweep_f64_internal(src, dst, h, w, ld, c, stream);
+            else
+                launch_levels_f64(src, dst, h, w, ld, c, lev, stream);
+            src = dst;
+        }
+    } else {
+        for (int j = 1; j <= n; ++j) {
+            double* dst = (j % 2) ? b : a;
+            launch_sweep_f64_internal(src, dst, h, w, ld, c, stream);
+            src = dst;
+        }
+    }
+    launch_sweep_f64_internal(src, src == a ? b : a, h, w, ld, c, stream);
+    return check_launch();
+}
+
 // FP64 sweep launch for other parts of the library (no argument checks).
 void launch_sweep_f64_internal(const double* in, double* out, int H, int W, int64_t ld, double c, hipStream_t s) {
     const bool vec_ok = (((uintptr_t)in | (uintptr_t)out) % 16 == 0) && (ld % 2 == 0);
@@ -343,6 +391,11 @@ sten_status sten_fill_rect_f64(double* grid, int64_t H, int64_t W, int64_t ld, i
     const uint32_t blocks = (uint32_t)std::min<int64_t>((total + 255) / 256, 65536);
     fill_rect_kernel<<<blocks, 256, 0, stream>>>(grid, ld, (int)r0, (int)r1, (int)c0, (int)c1, value);
     return check_launch();
+}
+
+sten_status sten_sweep_chain_f64(double* a, double* b, int64_t H, int64_t W, int64_t ld, int32_t m, double c,
+                                 hipStream_t stream) {
+    return sten::run_chain_f64(a, b, H, W, ld, m, c, stream);
 }
 
 sten_status sten_sweep_f64(const double* src, double* dst, int64_t H, int64_t W, int64_t ld, double c,

@@ -615,6 +615,13 @@ void launch_stream_grids_f64(const GridView<double>* views, int n, double c, int
                                                            s);
 }
 
+// One blocked launch of `levels` sweeps (1..12) from in to out, FP64 (no
+// argument checks; 16-byte aligned data, even ld, rows below 2^27 elements).
+void launch_levels_f64(const double* in, double* out, int H, int W, int64_t ld, double c, int levels,
+                       hipStream_t s) {
+    launch_levels<double, 2>(in, out, H, W, ld, c, levels, s);
+}
+
 // Entry used by the plain calls when they pick the blocked schedule.
 sten_status run_tb_f64(const double* u0, double* out, double* work, int64_t H, int64_t W, int64_t ld, int32_t T,
                        double c, int32_t levels, hipStream_t stream) {

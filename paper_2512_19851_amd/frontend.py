@@ -26,7 +26,14 @@ What it does, following Section III-A/III-B of the paper:
   side keeps building the next DAG while the GPU executes the previous one
   (pipelining);
 * before execution, consecutive nodes with the same output region and no path
-  between them are fused (node fusion).
+  between them are fused (node fusion);
+* a run of consecutive Jacobi nodes over the whole interior that ping-pong
+  between two arrays (the listing's loop) runs as one chain of blocked
+  launches (several iterations per pass over HBM) when both arrays' boundary
+  rings are known to hold the same values. The frontend knows a ring from the
+  fill nodes that wrote it (arrays start as zeros); any other write to a ring,
+  ``Context.invalidate(array)``, or ``Array.tensor()`` (which hands the data
+  out) makes it unknown. Both arrays end as after one node at a time.
 
 Backend: recognised ASTs map to hand-written libsten kernels - scalar fills
 -> ``sten_fill_rect_f64``; the listing's update ``c*(N + S + W + E)`` on any
@@ -42,6 +49,7 @@ for all ASTs (Section III-C).
 from __future__ import annotations
 
 import itertools
+import struct
 from dataclasses import dataclass, field
 
 __all__ = ["Context", "Array", "InPlaceDependencyError"]
@@ -179,6 +187,17 @@ def _structure(e: Expr, names: dict) -> str:
 
 _uids = itertools.count()
 
+# An array's boundary ring in 8 parts: 4 corners, then the rest of the top and bottom rows and of the left
+# and right columns. Array.ring holds, per part, the packed FP64 bits of the one value the whole part is
+# known to hold, or None when unknown; it is None for grids without an interior (fewer than 3 rows or
+# columns), which are not tracked.
+_ZERO_BITS = struct.pack("<d", 0.0)
+
+
+def _ring_parts(H: int, W: int) -> tuple:
+    return ((0, 1, 0, 1), (0, 1, W - 1, W), (H - 1, H, 0, 1), (H - 1, H, W - 1, W),
+            (0, 1, 1, W - 1), (H - 1, H, 1, W - 1), (1, H - 1, 0, 1), (1, H - 1, W - 1, W))
+
 
 class Array:
     """A lazily computed FP64 grid owned by a Context."""
@@ -187,7 +206,9 @@ class Array:
         self.ctx = ctx
         self.shape = (int(shape[0]), int(shape[1]))
         self.uid = next(_uids)
-        self.data = ctx.backend.alloc(self.shape)
+        self.data = ctx.backend.alloc(self.shape)  # zeros
+        H, W = self.shape
+        self.ring = (_ZERO_BITS,) * 8 if H >= 3 and W >= 3 else None
 
     def _region(self, key) -> tuple:
         if not isinstance(key, tuple) or len(key) != 2:
@@ -203,8 +224,10 @@ class Array:
         self.ctx._assign(self, self._region(key), _wrap(value))
 
     def tensor(self):
-        """The array's data after everything queued so far has run (syncs the context)."""
+        """The array's data after everything queued so far has run (syncs the context). The caller may
+        write to it, so the frontend forgets what it knew of the array's ring."""
         self.ctx.sync()
+        self.ctx.invalidate(self)
         return self.data
 
 
@@ -217,6 +240,7 @@ class Node:
     ast: str
     deps: set = field(default_factory=set)  # indices of earlier nodes in the same DAG
     depth: int = 1
+    chain_ok: bool = False  # whole interior, read from one array with the same known ring as `out`
 
 
 class Context:
@@ -230,7 +254,7 @@ class Context:
         self.backend = backend if backend is not None else GpuBackend()
         self.nodes: list[Node] = []
         self.asts: dict[str, int] = {}
-        self.stats = {"nodes": 0, "flushes": 0, "launch_groups": 0, "fused_nodes": 0}
+        self.stats = {"nodes": 0, "flushes": 0, "launch_groups": 0, "fused_nodes": 0, "chained_nodes": 0}
         # per array (uid): indices of the current DAG's nodes that write it / read it
         self._writers: dict[int, list] = {}
         self._readers: dict[int, list] = {}
@@ -254,6 +278,12 @@ class Context:
         ast = _structure(expr, {})
         self.asts[ast] = self.asts.get(ast, 0) + 1
         node = Node(out, region, expr, ins, ast)
+        H, W = out.shape
+        # cheap precondition of a chain here (whole interior, one other array with the same known ring);
+        # the Jacobi pattern itself is matched at flush time
+        node.chain_ok = out.ring is not None and region == (1, H - 1, 1, W - 1) and len(ins) > 0 and \
+            all(a is ins[0] for a in ins) and ins[0].ring == out.ring and None not in out.ring
+        self._update_ring(out, region, expr)
         in_uids = {a.uid for a in ins}
         for u in in_uids:                                       # true dependences (read after write)
             node.deps.update(self._writers.get(u, ()))
@@ -273,6 +303,51 @@ class Context:
 
     def depth(self) -> int:
         return max((n.depth for n in self.nodes), default=0)
+
+    # -- boundary rings -----------------------------------------------------
+    @staticmethod
+    def _update_ring(out: Array, region: tuple, expr: Expr) -> None:
+        """A write to `region` of `out`: a fill covering a ring part sets it; any other touch forgets it."""
+        if out.ring is None:
+            return
+        r0, r1, c0, c1 = region
+        if r0 >= r1 or c0 >= c1:
+            return
+        value = struct.pack("<d", float(expr.value)) if isinstance(expr, Const) else None
+        ring = list(out.ring)
+        for k, (a0, a1, b0, b1) in enumerate(_ring_parts(*out.shape)):
+            if r1 <= a0 or a1 <= r0 or c1 <= b0 or b1 <= c0:
+                continue
+            covers = r0 <= a0 and a1 <= r1 and c0 <= b0 and b1 <= c1
+            ring[k] = value if covers else None
+        out.ring = tuple(ring)
+
+    def invalidate(self, array: Array) -> None:
+        """Forget what is known of `array`'s ring (call after writing its data outside the frontend)."""
+        if array.ring is not None:
+            array.ring = (None,) * 8
+
+    def _chain_at(self, groups: list, i: int) -> list:
+        """Node indices of the Jacobi chain that starts at group i (at least 2 nodes), else []."""
+        chain = []
+        prev = None
+        for g in groups[i:]:
+            if len(g) != 1:
+                break
+            n = self.nodes[g[0]]
+            if not n.chain_ok:
+                break
+            jac = match_jacobi(n)
+            if jac is None or jac[0].shape != n.out.shape:
+                break
+            src, c = jac
+            if prev is not None:
+                psrc, pout, pc = prev
+                if src is not pout or n.out is not psrc or struct.pack("<d", c) != struct.pack("<d", pc):
+                    break
+            chain.append(g[0])
+            prev = (src, n.out, c)
+        return chain if len(chain) >= 2 else []
 
     # -- execution ----------------------------------------------------------
     def _groups(self) -> list[list[int]]:
@@ -296,11 +371,21 @@ class Context:
         if not self.nodes:
             return
         groups = self._groups()
-        for g in groups:
+        i = 0
+        while i < len(groups):
+            chain = self._chain_at(groups, i) if hasattr(self.backend, "run_chain") else []
+            if chain:
+                self.backend.run_chain([self.nodes[k] for k in chain])
+                self.stats["launch_groups"] += 1
+                self.stats["chained_nodes"] += len(chain)
+                i += len(chain)
+                continue
+            g = groups[i]
             self.backend.run([self.nodes[k] for k in g])
             self.stats["launch_groups"] += 1
             if len(g) > 1:
                 self.stats["fused_nodes"] += len(g)
+            i += 1
         self.nodes = []
         self._writers.clear()
         self._readers.clear()
@@ -530,6 +615,21 @@ class GpuBackend:
         for text, ins, outs, rows, cols in progs:
             self.ops.expr_run(text, [(a.data, r0, c0) for a, r0, c0 in ins],
                               [(a.data, r0, c0) for a, r0, c0 in outs], rows, cols)
+
+    def run_chain(self, chain: list) -> None:
+        """Jacobi nodes ping-ponging between two arrays with equal rings: one libsten chain call."""
+        from . import _lib
+        from .ops import _ld, _stream_ptr
+
+        a, c = match_jacobi(chain[0])
+        b = chain[0].out
+        H, W = b.shape
+        if a.data.stride() != b.data.stride():
+            for n in chain:
+                self.run([n])
+            return
+        _lib.call("sten_sweep_chain_f64", a.data.data_ptr(), b.data.data_ptr(), H, W, _ld(a.data), len(chain),
+                  float(c), _stream_ptr())
 
     def synchronize(self) -> None:
         self.torch.cuda.synchronize()

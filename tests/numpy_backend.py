@@ -9,12 +9,15 @@ one array fuse), so group structure can be checked on the CPU.
 
 import numpy as np
 
+import oracle
 from paper_2512_19851_amd import frontend as fe
 
 
 class NumpyBackend:
-    def __init__(self):
+    def __init__(self, chain_levels: int = 10):
         self.groups = []
+        self.chains = []
+        self.chain_levels = chain_levels
 
     def alloc(self, shape):
         return np.zeros(shape)
@@ -44,6 +47,35 @@ class NumpyBackend:
         for n, v in zip(group, vals):
             r0, r1, c0, c1 = n.region
             n.out.data[r0:r1, c0:c1] = v
+
+    def run_chain(self, chain):
+        """A model of the library's chain plan on the CPU: the first m-1 sweeps as k blocked passes (each pass
+        is `lev` sweeps of the oracle from the pass's source, that array's ring at every level), k chosen with
+        the parity that ends in the array of iterate m-1, then one plain sweep."""
+        a, c = fe.match_jacobi(chain[0])
+        b = chain[0].out
+        m = len(chain)
+        self.chains.append(m)
+        L = self.chain_levels
+        n = m - 1
+        src = a
+        if L > 1 and n >= 2:
+            k = -(-n // L)
+            if k % 2 != n % 2:
+                k += 1
+            base, extra = divmod(n, k)
+            for j in range(1, k + 1):
+                dst = b if j % 2 else a
+                lev = base + (1 if j <= extra else 0)
+                dst.data[1:-1, 1:-1] = oracle.jacobi5(src.data, lev, c)[1:-1, 1:-1]
+                src = dst
+        else:
+            for j in range(1, n + 1):
+                dst = b if j % 2 else a
+                dst.data[1:-1, 1:-1] = oracle.jacobi5(src.data, 1, c)[1:-1, 1:-1]
+                src = dst
+        dst = b if src is a else a
+        dst.data[1:-1, 1:-1] = oracle.jacobi5(src.data, 1, c)[1:-1, 1:-1]
 
     def synchronize(self):
         pass

@@ -127,3 +127,105 @@ def test_unsupported_strided_view():
     a = ctx.create_array((8, 8))
     with pytest.raises(NotImplementedError):
         a[::2, :]
+
+
+def numpy_listing_pair(H, W, T, ring2=1.0):
+    u1 = np.zeros((H, W))
+    u2 = np.zeros((H, W))
+    for u, v in ((u1, 1.0), (u2, ring2)):
+        u[0, :] = u[-1, :] = u[:, 0] = u[:, -1] = v
+    for _ in range(T):
+        u2[1:-1, 1:-1] = 0.25 * (u1[:-2, 1:-1] + u1[2:, 1:-1] + u1[1:-1, :-2] + u1[1:-1, 2:])
+        u1, u2 = u2, u1
+    return u1, u2
+
+
+def listing_pair(ctx, H, W, T, ring2=1.0):
+    u1 = ctx.create_array((H, W))
+    u2 = ctx.create_array((H, W))
+    u1[0, :] = u1[-1, :] = u1[:, 0] = u1[:, -1] = 1
+    u2[0, :] = u2[-1, :] = u2[:, 0] = u2[:, -1] = ring2
+    for _ in range(T):
+        u2[1:-1, 1:-1] = 0.25 * (u1[:-2, 1:-1] + u1[2:, 1:-1] + u1[1:-1, :-2] + u1[1:-1, 2:])
+        u1, u2 = u2, u1
+    ctx.sync()
+    return u1, u2
+
+
+def test_ring_tracking():
+    ctx = fe.Context(backend=NumpyBackend())
+    z = fe._ZERO_BITS
+    one = fe.struct.pack("<d", 1.0)
+    a = ctx.create_array((5, 6))
+    assert a.ring == (z,) * 8                      # arrays start as zeros
+    a[0, :] = 1.0                                  # top row: both top corners and the top part
+    assert a.ring[0] == a.ring[1] == a.ring[4] == one and a.ring[2] == z
+    a[1:3, 0] = 2.0                                # part of the left column: unknown
+    assert a.ring[6] is None and a.ring[0] == one
+    a[:, 0] = -0.0                                 # the whole left column, corners included
+    assert a.ring[6] == a.ring[0] == a.ring[2] == fe.struct.pack("<d", -0.0) != z
+    a[1:-1, 1:-1] = 3.0                            # interior only: ring untouched
+    assert a.ring[6] is not None
+    b = ctx.create_array((5, 6))
+    c = ctx.create_array((5, 6))
+    b[0:2, 0:2] = c[1:3, 1:3] + 1.0                # an expression touching the top-left corner
+    assert b.ring[0] is None and b.ring[4] is None and b.ring[6] is None and b.ring[1] == z
+    ctx.invalidate(b)
+    assert b.ring == (None,) * 8
+    a.tensor()                                     # handed out: forgotten
+    assert a.ring == (None,) * 8
+    assert ctx.create_array((2, 9)).ring is None   # no interior: not tracked
+
+
+@pytest.mark.parametrize("levels", [1, 2, 3, 10])
+@pytest.mark.parametrize("depth", [1, 2, 7, 1000])
+def test_listing_chains_keep_both_arrays(levels, depth):
+    """Chains of Jacobi nodes (the library's plan modelled on the CPU) leave both arrays as one node at a
+    time would: iterate T in one, iterate T-1 in the other."""
+    for T in (1, 2, 3, 9, 10, 11, 25):
+        be = NumpyBackend(chain_levels=levels)
+        ctx = fe.Context(max_depth=depth, backend=be)
+        u1, u2 = listing_pair(ctx, 9, 12, T)
+        w1, w2 = numpy_listing_pair(9, 12, T)
+        assert np.array_equal(u1.data, w1) and np.array_equal(u2.data, w2), (levels, depth, T)
+        if depth == 1 or T == 1:
+            assert ctx.stats["chained_nodes"] == 0
+        elif depth >= 1000:
+            assert ctx.stats["chained_nodes"] == T and be.chains == [T]
+
+
+def test_no_chain_when_rings_differ():
+    be = NumpyBackend()
+    ctx = fe.Context(max_depth=1000, backend=be)
+    u1, u2 = listing_pair(ctx, 8, 10, 12, ring2=2.0)
+    w1, w2 = numpy_listing_pair(8, 10, 12, ring2=2.0)
+    assert np.array_equal(u1.data, w1) and np.array_equal(u2.data, w2)
+    assert ctx.stats["chained_nodes"] == 0 and not be.chains
+
+
+def test_no_chain_after_data_handed_out():
+    be = NumpyBackend()
+    ctx = fe.Context(max_depth=1000, backend=be)
+    u1 = ctx.create_array((8, 8))
+    u2 = ctx.create_array((8, 8))
+    for u in (u1, u2):
+        u[0, :] = u[-1, :] = u[:, 0] = u[:, -1] = 1.0
+    u2.tensor()[0, 3] = 7.0  # written outside the frontend
+    for _ in range(4):
+        u2[1:-1, 1:-1] = 0.25 * (u1[:-2, 1:-1] + u1[2:, 1:-1] + u1[1:-1, :-2] + u1[1:-1, 2:])
+        u1, u2 = u2, u1
+    ctx.sync()
+    assert ctx.stats["chained_nodes"] == 0
+
+
+def test_no_chain_for_partial_regions_or_other_coefficients():
+    be = NumpyBackend()
+    ctx = fe.Context(max_depth=1000, backend=be)
+    a = ctx.create_array((8, 8))
+    b = ctx.create_array((8, 8))
+    b[1:-2, 1:-1] = 0.25 * (a[:-3, 1:-1] + a[2:-1, 1:-1] + a[1:-2, :-2] + a[1:-2, 2:])
+    a[1:-2, 1:-1] = 0.25 * (b[:-3, 1:-1] + b[2:-1, 1:-1] + b[1:-2, :-2] + b[1:-2, 2:])
+    b[1:-1, 1:-1] = 0.25 * (a[:-2, 1:-1] + a[2:, 1:-1] + a[1:-1, :-2] + a[1:-1, 2:])
+    a[1:-1, 1:-1] = 0.5 * (b[:-2, 1:-1] + b[2:, 1:-1] + b[1:-1, :-2] + b[1:-1, 2:])
+    ctx.sync()
+    assert ctx.stats["chained_nodes"] == 0

@@ -97,3 +97,59 @@ def test_in_place_rejected_on_gpu(fe):
     a = ctx.create_array((8, 8))
     with pytest.raises(fe.InPlaceDependencyError):
         a[1:-1, 1:-1] = 0.25 * (a[:-2, 1:-1] + a[2:, 1:-1] + a[1:-1, :-2] + a[1:-1, 2:])
+
+
+@pytest.mark.parametrize("shape,T,depth", [((64, 64), 25, 1000), ((300, 517), 23, 7), ((257, 1030), 31, 1000),
+                                           ((3, 130), 5, 1000), ((1000, 1000), 40, 12)])
+def test_listing_chains_keep_both_arrays(fe, shape, T, depth):
+    """The listing's Jacobi nodes run as chains of blocked launches; both arrays end as after one node at a
+    time (iterate T and iterate T-1)."""
+    ctx = fe.Context(max_depth=depth)
+    H, W = shape
+    u1 = ctx.create_array((H, W))
+    u2 = ctx.create_array((H, W))
+    u1[0, :] = u1[-1, :] = u1[:, 0] = u1[:, -1] = 1
+    u2[0, :] = u2[-1, :] = u2[:, 0] = u2[:, -1] = 1
+    for _ in range(T):
+        u2[1:-1, 1:-1] = 0.25 * (u1[:-2, 1:-1] + u1[2:, 1:-1] + u1[1:-1, :-2] + u1[1:-1, 2:])
+        u1, u2 = u2, u1
+    say(f"frontend chains {shape} T={T} depth={depth}")
+    ctx.sync()
+    assert ctx.stats["chained_nodes"] > 0 or H < 3
+    u0 = unit_ring_grid(H, W)
+    assert np.array_equal(to_host(u1.tensor()), oracle.jacobi5(u0, T))
+    assert np.array_equal(to_host(u2.tensor()), oracle.jacobi5(u0, T - 1))
+
+
+@pytest.mark.parametrize("schedule", [0, 1, 2, 3, 12])
+def test_sweep_chain_abi(schedule):
+    """sten_sweep_chain_f64 on two arrays with equal rings, random interiors, every chain length 0..24 and
+    the schedule's levels; odd widths take single sweeps."""
+    import torch
+
+    device()
+    from paper_2512_19851_amd import _lib, ops
+
+    try:
+        ops.set_schedule(schedule)
+        for H, W in ((5, 7), (64, 66), (130, 257), (41, 512)):
+            a0 = np.random.default_rng(H * W + schedule).standard_normal((H, W))
+            b0 = np.random.default_rng(H + W).standard_normal((H, W))
+            b0[0, :], b0[-1, :], b0[:, 0], b0[:, -1] = a0[0, :], a0[-1, :], a0[:, 0], a0[:, -1]
+            states = [a0]
+            for _ in range(24):
+                states.append(oracle.jacobi5(states[-1], 1))
+            for m in range(0, 25):
+                say(f"chain abi schedule={schedule} {H}x{W} m={m}")
+                a = torch.from_numpy(a0.copy()).cuda()
+                b = torch.from_numpy(b0.copy()).cuda()
+                _lib.call("sten_sweep_chain_f64", a.data_ptr(), b.data_ptr(), H, W, W, m, 0.25,
+                          torch.cuda.current_stream().cuda_stream)
+                last, other = (b, a) if m % 2 else (a, b)
+                if m == 0:
+                    assert np.array_equal(to_host(a), a0) and np.array_equal(to_host(b), b0)
+                    continue
+                assert np.array_equal(to_host(last), states[m]), (schedule, H, W, m)
+                assert np.array_equal(to_host(other), states[m - 1]), (schedule, H, W, m)
+    finally:
+        ops.set_schedule(0)
