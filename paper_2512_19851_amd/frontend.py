@@ -169,6 +169,20 @@ def _refs(e: Expr, acc: list) -> list:
     return acc
 
 
+def _walk(e: Expr, names: dict, refs: list) -> str:
+    """One pass over an expression: collects its slice references in order and returns the
+    parameterised AST text (as _structure)."""
+    if isinstance(e, Ref):
+        refs.append(e)
+        k = names.setdefault(e.array.uid, f"A{len(names)}")
+        return f"{k}[{e.region}]"
+    if isinstance(e, BinOp):
+        return f"({_walk(e.a, names, refs)}{e.op}{_walk(e.b, names, refs)})"
+    if isinstance(e, Const):
+        return repr(e.value)
+    return f"{e.op}({_walk(e.a, names, refs)})"
+
+
 def _structure(e: Expr, names: dict) -> str:
     """Parameterised AST text: arrays become placeholders in order of first use."""
     if isinstance(e, Const):
@@ -255,8 +269,12 @@ class Context:
         self.nodes: list[Node] = []
         self.asts: dict[str, int] = {}
         self.stats = {"nodes": 0, "flushes": 0, "launch_groups": 0, "fused_nodes": 0, "chained_nodes": 0}
-        # per array (uid): indices of the current DAG's nodes that write it / read it
-        self._writers: dict[int, list] = {}
+        # per array (uid), in the current DAG: the last node that wrote it, and the nodes that read it
+        # since. Earlier writers and readers are reached through these (a later write of an array depends
+        # on its earlier writers and readers), so depths and the fusion test (within runs of consecutive
+        # nodes) are the same as with every per-array edge, at a cost per node that does not grow with
+        # the DAG.
+        self._writers: dict[int, int] = {}
         self._readers: dict[int, list] = {}
 
     def create_array(self, shape) -> Array:
@@ -265,17 +283,20 @@ class Context:
     # -- recording ----------------------------------------------------------
     def _assign(self, out: Array, region: tuple, expr: Expr) -> None:
         shape = (region[1] - region[0], region[3] - region[2])
-        for r in _refs(expr, []):
-            if (r.region[1] - r.region[0], r.region[3] - r.region[2]) != shape:
+        refs: list = []
+        ast = _walk(expr, {}, refs)
+        ins = []
+        for r in refs:
+            rr = r.region
+            if (rr[1] - rr[0], rr[3] - rr[2]) != shape:
                 raise ValueError(f"slice of shape {shape} assigned from a slice of another shape "
                                  "(broadcasting is not supported)")
-        ins = _arrays(expr, [])
-        if any(a is out for a in ins):
-            raise InPlaceDependencyError("the right side reads the array being assigned; use a second array")
-        for a in ins:
+            a = r.array
+            if a is out:
+                raise InPlaceDependencyError("the right side reads the array being assigned; use a second array")
             if a.ctx is not self:
                 raise ValueError("arrays of different contexts")
-        ast = _structure(expr, {})
+            ins.append(a)
         self.asts[ast] = self.asts.get(ast, 0) + 1
         node = Node(out, region, expr, ins, ast)
         H, W = out.shape
@@ -286,9 +307,11 @@ class Context:
         self._update_ring(out, region, expr)
         in_uids = {a.uid for a in ins}
         for u in in_uids:                                       # true dependences (read after write)
-            node.deps.update(self._writers.get(u, ()))
+            if u in self._writers:
+                node.deps.add(self._writers[u])
         node.deps.update(self._readers.get(out.uid, ()))       # anti dependences (write after read)
-        node.deps.update(self._writers.get(out.uid, ()))       # output dependences (write after write)
+        if out.uid in self._writers:                            # output dependences (write after write)
+            node.deps.add(self._writers[out.uid])
         node.depth = 1 + max((self.nodes[k].depth for k in node.deps), default=0)
         if node.depth > self.max_depth:
             self.flush()
@@ -298,7 +321,8 @@ class Context:
         self.nodes.append(node)
         for u in in_uids:
             self._readers.setdefault(u, []).append(k)
-        self._writers.setdefault(out.uid, []).append(k)
+        self._writers[out.uid] = k
+        self._readers[out.uid] = []
         self.stats["nodes"] += 1
 
     def depth(self) -> int:
