@@ -147,31 +147,9 @@ def _norm(s, n: int) -> tuple[int, int]:
     raise TypeError("indices must be ints or slices")
 
 
-def _arrays(e: Expr, acc: list) -> list:
-    if isinstance(e, Ref):
-        acc.append(e.array)
-    elif isinstance(e, BinOp):
-        _arrays(e.a, acc)
-        _arrays(e.b, acc)
-    elif isinstance(e, Unary):
-        _arrays(e.a, acc)
-    return acc
-
-
-def _refs(e: Expr, acc: list) -> list:
-    if isinstance(e, Ref):
-        acc.append(e)
-    elif isinstance(e, BinOp):
-        _refs(e.a, acc)
-        _refs(e.b, acc)
-    elif isinstance(e, Unary):
-        _refs(e.a, acc)
-    return acc
-
-
 def _walk(e: Expr, names: dict, refs: list) -> str:
     """One pass over an expression: collects its slice references in order and returns the
-    parameterised AST text (as _structure)."""
+    parameterised AST text (arrays become placeholders A0, A1, ... in order of first use)."""
     if isinstance(e, Ref):
         refs.append(e)
         k = names.setdefault(e.array.uid, f"A{len(names)}")
@@ -181,18 +159,6 @@ def _walk(e: Expr, names: dict, refs: list) -> str:
     if isinstance(e, Const):
         return repr(e.value)
     return f"{e.op}({_walk(e.a, names, refs)})"
-
-
-def _structure(e: Expr, names: dict) -> str:
-    """Parameterised AST text: arrays become placeholders in order of first use."""
-    if isinstance(e, Const):
-        return repr(e.value)
-    if isinstance(e, Ref):
-        k = names.setdefault(e.array.uid, f"A{len(names)}")
-        return f"{k}[{e.region}]"
-    if isinstance(e, Unary):
-        return f"{e.op}({_structure(e.a, names)})"
-    return f"({_structure(e.a, names)}{e.op}{_structure(e.b, names)})"
 
 
 # ---------------------------------------------------------------------------
