@@ -72,8 +72,8 @@ int sten_last_hip_error(void);
  * Bit-exact with the sweep evaluated in FP64 in the listing's order (no fused
  * multiply-add, no reassociation). Schedule: when the three grids are 16-byte
  * aligned with an even ld and T >= 2, several sweeps run per launch
- * (temporal blocking, at most 10 (FP64) or 8 (FP32) by default, T split evenly
- * over the launches; see sten_tune_schedule), else one sweep
+ * (temporal blocking, at most 12 (FP64) or 8-12 (FP32, by grid size) by
+ * default, T split evenly over the launches; see sten_tune_schedule), else one sweep
  * per launch; both give the same bits. Errors: STEN_ERR_ARG, STEN_ERR_PTR,
  * STEN_ERR_ALIAS (any two of u0, out, work overlap), STEN_ERR_HIP.
  */
@@ -156,8 +156,9 @@ sten_status sten_fill_rect_f64(double* grid, int64_t H, int64_t W, int64_t ld, i
 
 /* Schedule hook for sten_jacobi5_f64 / _f32: sweeps per launch (1: one sweep
  * per launch, the paper's one kernel per iteration; 2..12: temporal blocking
- * with at most that many; 0: built-in, 10 for FP64, 8 for FP32). Process-wide.
- * Same bits for every value. */
+ * with at most that many; 0: built-in, 12 for FP64, and for FP32 8 while one
+ * buffer is at most 128 MiB, else 12). The T sweeps are split evenly over
+ * ceil(T / levels) launches. Process-wide. Same bits for every value. */
 sten_status sten_tune_schedule(int32_t levels);
 
 /* Tuning hook: output rows per workgroup tile of the sweep kernels (4, 8 or
