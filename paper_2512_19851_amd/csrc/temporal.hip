@@ -360,8 +360,13 @@ __device__ __forceinline__ void stream_tile(const T* __restrict__ in, T* __restr
         stream_band<T, V, TL, A, 2>(in, out, H, W, ld, c, cs, olo, ohi, rb, re, dir);
 }
 
+// FP64: keep 3 waves per SIMD (at most 168 VGPRs). The 12-level kernel needs
+// 169 otherwise and would drop to 2; under the cap it spills one 8-byte value,
+// stored once per wave and reloaded once per band, outside the row loop.
+#define STEN_STREAM_OCCUPANCY __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 1)))
+
 template <typename T, int V, int TL, int A>
-__global__ __launch_bounds__(64) void sweep_stream_kernel(const T* __restrict__ in, T* __restrict__ out, int H, int W,
+__global__ __launch_bounds__(64) STEN_STREAM_OCCUPANCY void sweep_stream_kernel(const T* __restrict__ in, T* __restrict__ out, int H, int W,
                                                          int64_t ld, T c, uint32_t strips, int band, int flush) {
     stream_tile<T, V, TL, A>(in, out, H, W, ld, c, strips, band, flush, xcd_tile_of_block(blockIdx.x, gridDim.x));
 }
@@ -388,7 +393,7 @@ struct StreamGrids {
 };
 
 template <typename T, int V, int TL, int A>
-__global__ __launch_bounds__(64) void sweep_stream_grids_kernel(const StreamGrids<T> grids, T c) {
+__global__ __launch_bounds__(64) STEN_STREAM_OCCUPANCY void sweep_stream_grids_kernel(const StreamGrids<T> grids, T c) {
     const uint32_t b = xcd_tile_of_block(blockIdx.x, gridDim.x);
     int k = 0;
     while (k + 1 < grids.n && b >= grids.g[k + 1].first) ++k;
