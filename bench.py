@@ -345,9 +345,9 @@ def bench_tiled(ops, n: int, T: int, args, plain_sec_per_step: float, blocked_se
     want = ops.jacobi5(u0, T)
     comm = torch.cuda.Stream()
     res = {}
-    cases = ((2, 2, 1, "packed", True), (4, 4, 1, "packed", True), (2, 2, 10, "packed", True),
-             (2, 2, 10, "packed", False), (2, 2, 10, "direct", False), (4, 4, 10, "direct", False),
-             (8, 8, 10, "direct", False))
+    cases = ((2, 2, 1, "packed", True), (4, 4, 1, "packed", True), (2, 2, 12, "packed", True),
+             (2, 2, 12, "packed", False), (2, 2, 12, "direct", False), (4, 4, 12, "direct", False),
+             (8, 8, 12, "direct", False))
     for pr, pc, g, mode, two_streams in cases:
         t = ops.TiledGrid(n, n, pr, pc, comm_stream=comm if two_streams else None, ghost=g, exchange=mode)
         t.scatter(u0)
@@ -376,7 +376,8 @@ def bench_tiled(ops, n: int, T: int, args, plain_sec_per_step: float, blocked_se
                        "depth g; exchange packed (pack + unpack kernels through send buffers) or direct (one "
                        "copy kernel), on a second stream (2stream) or the compute stream (1stream); g = 1: one "
                        "exchange and one sweep kernel per tile per sweep; g > 1: one exchange and one blocked "
-                       "launch over all tiles per chunk of up to g sweeps")
+                       "launch over all tiles (per 32 tiles) per chunk of up to g sweeps, the sweeps split "
+                       "evenly over the chunks")
     return res
 
 
