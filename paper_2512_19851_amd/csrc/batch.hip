@@ -174,27 +174,29 @@ __device__ __forceinline__ void run_global(const Desc& d, int T, float c) {
 // in order with the previous row's old values kept in `prev` (in-place
 // rolling update). Rows past the grid are dummies: loaded as 0, never
 // computed, never stored.
-constexpr int kRegVs[3] = {1, 2, 4};
-constexpr int kRegRs[5] = {1, 2, 4, 8, 16};
+constexpr int kRegMaxV = 4;   // columns per lane: a row of up to 256 columns per wave
+constexpr int kRegMaxR = 16;  // rows per lane
 
 struct RegShape {
     int V, R;  // columns and rows per lane (0: the grid does not fit)
 };
 
+// The smallest lane tile that covers the grid: V = ceil(W / 64) columns and
+// R = ceil(H / waves) rows per lane (rounded up to a row count with a kernel
+// variant). Every lane computes its whole tile each
+// sweep (points past the grid are computed and dropped), so sweep time
+// follows V * R, not the grid's point count: a tight tile keeps a 130 x 130
+// grid from costing as much as a 256 x 256 one.
 __device__ __host__ inline RegShape reg_shape(int H, int W, int block) {
     const int nw = block / 64;
     RegShape s{0, 0};
-    for (int v : kRegVs) {
-        if (64 * v < W) continue;
-        for (int r : kRegRs) {
-            if (nw * r >= H && v * r <= 64) {
-                s.V = v;
-                s.R = r;
-                return s;
-            }
-        }
-        break;
-    }
+    const int v = (W + 63) / 64;
+    int r = (H + nw - 1) / nw;
+    if (v < 1 || v > kRegMaxV || r < 1 || r > kRegMaxR) return s;
+    // row counts with a kernel variant: 1..8, 10, 12, 16 (all 16 spill when inlined together)
+    if (r > 8) r = r <= 10 ? 10 : (r <= 12 ? 12 : 16);
+    s.V = v;
+    s.R = r;
     return s;
 }
 
@@ -290,9 +292,12 @@ __device__ __forceinline__ void run_reg_any(const Desc& d, int T, float c, float
     switch (code) {
 #define STEN_REG_CASE(V_, R_) \
     case V_ * 32 + R_: run_reg<V_, R_>(d, T, c, lds); break;
-        STEN_REG_CASE(1, 1) STEN_REG_CASE(1, 2) STEN_REG_CASE(1, 4) STEN_REG_CASE(1, 8) STEN_REG_CASE(1, 16)
-        STEN_REG_CASE(2, 1) STEN_REG_CASE(2, 2) STEN_REG_CASE(2, 4) STEN_REG_CASE(2, 8) STEN_REG_CASE(2, 16)
-        STEN_REG_CASE(4, 1) STEN_REG_CASE(4, 2) STEN_REG_CASE(4, 4) STEN_REG_CASE(4, 8) STEN_REG_CASE(4, 16)
+#define STEN_REG_ROWS(V_)                                                                                     \
+    STEN_REG_CASE(V_, 1) STEN_REG_CASE(V_, 2) STEN_REG_CASE(V_, 3) STEN_REG_CASE(V_, 4) STEN_REG_CASE(V_, 5)   \
+    STEN_REG_CASE(V_, 6) STEN_REG_CASE(V_, 7) STEN_REG_CASE(V_, 8) STEN_REG_CASE(V_, 10) STEN_REG_CASE(V_, 12) \
+    STEN_REG_CASE(V_, 16)
+        STEN_REG_ROWS(1) STEN_REG_ROWS(2) STEN_REG_ROWS(3) STEN_REG_ROWS(4)
+#undef STEN_REG_ROWS
 #undef STEN_REG_CASE
         default: break;
     }
