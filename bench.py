@@ -619,13 +619,15 @@ def main() -> int:
     ap.add_argument("--cpu-budget", type=float, default=16.0, help="seconds of CPU oracle work")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extensions", action="store_true")
-    ap.add_argument("--mode", choices=["step", "sweep", "copy", "hilo", "tb", "cavity", "pressure"], default="step",
+    ap.add_argument("--mode", choices=["step", "sweep", "copy", "hilo", "tb", "cavity", "pressure", "batch"],
+                    default="step",
                     help="step: the benchmark; sweep: only --kernel-reps sweep launches; "
                          "copy: only --kernel-reps plain grid copies (counter calibration); "
                          "hilo: only --kernel-reps hi/lo sweeps on encoded grids; "
                          "tb: only --kernel-reps temporally blocked launches; "
                          "cavity: only the cavity-flow extension (--n grid side); "
-                         "pressure: only --kernel-reps blocked passes of 8 cavity pressure iterations (--n)")
+                         "pressure: only --kernel-reps blocked passes of 8 cavity pressure iterations (--n); "
+                         "batch: only the batched extension (--sweeps, --steps graph replays)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -647,6 +649,11 @@ def main() -> int:
         return 0
     if args.mode == "pressure":
         print(json.dumps(bench_pressure_passes(args.n, args.kernel_reps)), flush=True)
+        return 0
+    if args.mode == "batch":
+        from paper_2512_19851_amd import ops
+
+        print(json.dumps({"mode": "batch", **bench_batch(ops, args.sweeps, args)}), flush=True)
         return 0
     n, T = args.n, args.sweeps
     log(f"[bench] generating {n}x{n} FP64 N(0,1) seed 0")
