@@ -789,6 +789,25 @@ def main() -> int:
                 "launch time (the arithmetic floor, 4 FP64 ops per point per sweep at the 39.3 Tops/s "
                 "add/multiply rate, is lower)",
     }
+    # The ALU view of the same launches: 4 FP64 adds/multiplies per interior point per sweep against the
+    # chip's FP64 add/multiply issue rate (256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 Tops/s; FMA counts
+    # twice in the 78.6 TFLOP/s figure). A launch also issues 2 DPP lane shifts per point per level and
+    # recomputes the halo rows and columns its bands and strips share (measured tile: 1.25 x the rows,
+    # 128/104 x the columns), so the VALU issues about 4 x 1.5 x 1.54 = 9.2 lane-operations per useful point
+    # and level.
+    alu_peak = 256 * 4 * 16 * 2.4e9 / 1e12
+    alu_achieved = 4.0 * interior * T / (step_launch_ms * 1e-3 * launches) / 1e12
+    roofline["alu_view"] = {
+        "bound": "alu",
+        "achieved": round(alu_achieved, 2),
+        "peak": round(alu_peak, 2),
+        "unit": "Tops/s",
+        "frac": round(alu_achieved / alu_peak, 4),
+        "valu_issue_frac_estimate": round(alu_achieved * 9.24 / 4.0 / alu_peak, 3),
+        "note": "4 FP64 operations per interior point per sweep (3 adds, 1 multiply) over the step's launch "
+                "time; valu_issue_frac_estimate adds the DPP lane shifts and the halo recomputation "
+                "(9.2 VALU lane-operations per useful point and level)",
+    }
     # the dominant kernel alone (every launch TB_LEVELS sweeps), as the traffic counters see it
     w2 = torch.empty_like(u0)
     ops.set_schedule(TB_LEVELS)
