@@ -20,6 +20,11 @@ the listing of the Laplace solver in Section III-A):
                    and 64 distinct flat coordinates for finite differences
 * ``paper_grid``   the listing's initial state: unit boundary ring, zero
                    interior (16384x16384 per GPU in the paper's runs)
+* ``hashed_grid``  values from an integer hash of (seed, row, column), uniform
+                   in [-1, 1): a grid too large to draw on the host (past 2^31
+                   points) is filled on the device row block by row block with
+                   ``hashed_rows_torch``, and any window of it is rebuilt on the
+                   host with ``hashed_grid``, bit for bit
 """
 
 from __future__ import annotations
@@ -35,6 +40,8 @@ __all__ = [
     "batch_f32",
     "adjoint_f32",
     "unit_ring_grid",
+    "hashed_grid",
+    "hashed_rows_torch",
     "BATCH_COUNT",
 ]
 
@@ -118,3 +125,38 @@ def unit_ring_grid(H: int, W: int, dtype=np.float64) -> np.ndarray:
     u[:, 0] = 1
     u[:, -1] = 1
     return u
+
+
+# Integer hash of (seed, i, j) into [0, 2^32): two odd multipliers and xor-shifts,
+# all in 64-bit integers without overflow (i, j < 2^31, products < 2^63).
+_HM1, _HM2, _HM3, _HS = 0x9E3779B1, 0x85EBCA77, 0x2C1B3C6D, 0x27D4EB2F
+_M32 = 0xFFFFFFFF
+
+
+def _hash_to_unit(h):
+    # h in [0, 2^32) -> h / 2^31 - 1, exact in FP64
+    return h * (1.0 / 2147483648.0) - 1.0
+
+
+def hashed_grid(r0: int, r1: int, c0: int, c1: int, seed: int = 0) -> np.ndarray:
+    """Rows [r0, r1) and columns [c0, c1) of the hashed grid, FP64 in [-1, 1)."""
+    i = np.arange(r0, r1, dtype=np.int64)[:, None]
+    j = np.arange(c0, c1, dtype=np.int64)[None, :]
+    h = ((i * _HM1) ^ (j * _HM2) ^ (seed * _HS)) & _M32
+    h = h ^ (h >> 15)
+    h = (h * _HM3) & _M32
+    h = h ^ (h >> 12)
+    return _hash_to_unit(h.astype(np.float64))
+
+
+def hashed_rows_torch(r0: int, r1: int, W: int, device, seed: int = 0):
+    """Rows [r0, r1) (all W columns) of the hashed grid as an FP64 torch tensor on `device`."""
+    import torch
+
+    i = torch.arange(r0, r1, dtype=torch.int64, device=device)[:, None]
+    j = torch.arange(0, W, dtype=torch.int64, device=device)[None, :]
+    h = ((i * _HM1) ^ (j * _HM2) ^ (seed * _HS)) & _M32
+    h = h ^ (h >> 15)
+    h = (h * _HM3) & _M32
+    h = h ^ (h >> 12)
+    return _hash_to_unit(h.to(torch.float64))
