@@ -180,8 +180,9 @@ def test_large_f64_sampled_bench_config(ops):
     assert got.min() >= u0.min() and got.max() <= u0.max()
 
 
-def test_beyond_int32_points(ops):
-    """46400 x 46400 FP64: 2.15e9 points, past 2^31, 17.2 GB per buffer. Sampled outputs bit-exact
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_beyond_int32_points(ops, dtype):
+    """46400 x 46400: 2.15e9 points, past 2^31 (17.2 GB per FP64 buffer). Sampled outputs bit-exact
     with the oracle on their dependence cones after one launch (T = 12) and two (T = 23); row
     offsets beyond 32 bits on every kernel of the path (ring copy, sweeps, stores)."""
     import torch
@@ -190,12 +191,13 @@ def test_beyond_int32_points(ops):
 
     n = 46400
     dev = device()
-    say(f"beyond int32: fill {n}x{n}")
-    u0 = torch.empty((n, n), dtype=torch.float64, device=dev)
+    tdt = torch.float64 if dtype == np.float64 else torch.float32
+    say(f"beyond int32 {dtype.__name__}: fill {n}x{n}")
+    u0 = torch.empty((n, n), dtype=tdt, device=dev)
     for r0 in range(0, n, 2048):
-        u0[r0:min(n, r0 + 2048)] = hashed_rows_torch(r0, min(n, r0 + 2048), n, dev, seed=11)
+        u0[r0:min(n, r0 + 2048)] = hashed_rows_torch(r0, min(n, r0 + 2048), n, dev, seed=11).to(tdt)
     for T in (12, 23):
-        say(f"beyond int32: T={T}")
+        say(f"beyond int32 {dtype.__name__}: T={T}")
         got = ops.jacobi5(u0, T)
         pts = sample_points(n, n, 24, seed=T) + [(n - 2, n // 2), (n // 2, n - 2), (46341, 46341)]
         flat = torch.tensor([i * n + j for i, j in pts], dtype=torch.int64, device=dev)
@@ -204,7 +206,8 @@ def test_beyond_int32_points(ops):
         torch.cuda.empty_cache()
         for k, (i, j) in enumerate(pts):
             r0, r1, c0, c1 = cone_window(n, n, i, j, T)
-            sub = oracle.jacobi5(hashed_grid(r0, r1 + 1, c0, c1 + 1, seed=11), T)
+            win = hashed_grid(r0, r1 + 1, c0, c1 + 1, seed=11).astype(dtype)
+            sub = oracle.jacobi5(win, T, dtype=dtype)
             assert vals[k] == sub[i - r0, j - c0], f"T={T} point {(i, j)}"
 
 
