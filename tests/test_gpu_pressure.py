@@ -116,3 +116,36 @@ def test_pressure_unsupported_layouts(ops):
         with pytest.raises(_lib.StenError) as e:
             ops.cavity_pressure(d, d.clone(), 3, 0.25, 0.25, 0.1)
         assert e.value.name == "STEN_ERR_UNSUPPORTED"
+
+
+def test_pressure_beyond_int32_points(ops):
+    """46400 x 46400 (2.15e9 points, past 2^31; four 17.2 GB buffers): 9 iterations (two passes),
+    sampled outputs bit-exact with the oracle. A window reaching nit + 1 beyond a point (clamped to the
+    real walls) gives that point exactly: each iteration, and each wall rule, reads only distance 1."""
+    import torch
+
+    from tests.gpu_util import cone_window, sample_points
+    from workloads import hashed_grid, hashed_rows_torch
+
+    n, nit = 46400, 9
+    prm = oc.CavityParams(n, n, lx=2.0, ly=1.3)
+    dev = device()
+    say(f"pressure beyond int32: fill {n}x{n}")
+    p0 = torch.empty((n, n), dtype=torch.float64, device=dev)
+    b = torch.empty((n, n), dtype=torch.float64, device=dev)
+    for r0 in range(0, n, 2048):
+        r1 = min(n, r0 + 2048)
+        p0[r0:r1] = hashed_rows_torch(r0, r1, n, dev, seed=21)
+        b[r0:r1] = hashed_rows_torch(r0, r1, n, dev, seed=22)
+    say(f"pressure beyond int32: nit={nit}")
+    got = ops.cavity_pressure(p0, b, nit, prm.cw, prm.cn, prm.cb)
+    pts = sample_points(n, n, 24, seed=3) + [(n - 1, 7), (n - 2, n - 1), (0, n - 1), (46341, 0), (46341, 46341)]
+    flat = torch.tensor([i * n + j for i, j in pts], dtype=torch.int64, device=dev)
+    vals = to_host(got.view(-1)[flat])
+    del got, p0, b
+    torch.cuda.empty_cache()
+    for k, (i, j) in enumerate(pts):
+        r0, r1, c0, c1 = cone_window(n, n, i, j, nit)
+        want = _want(hashed_grid(r0, r1 + 1, c0, c1 + 1, seed=21), hashed_grid(r0, r1 + 1, c0, c1 + 1, seed=22),
+                     prm, nit)
+        assert vals[k] == want[i - r0, j - c0], f"point {(i, j)}"
