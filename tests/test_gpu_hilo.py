@@ -144,6 +144,32 @@ def test_hilo_full_size_T100_sampled(ops):
     assert worst <= 1e-10
 
 
+def test_hilo_beyond_int32_points(ops):
+    """46400 x 46400 (2.15e9 points, past 2^31): encode, 5 encoded sweeps and decode, sampled outputs
+    bit-exact with the model on their dependence cones."""
+    import torch
+
+    from workloads import hashed_grid, hashed_rows_torch
+
+    n, T = 46400, 5
+    dev = device()
+    say(f"hilo beyond int32: fill {n}x{n}")
+    u0 = torch.empty((n, n), dtype=torch.float64, device=dev)
+    for r0 in range(0, n, 2048):
+        u0[r0:min(n, r0 + 2048)] = hashed_rows_torch(r0, min(n, r0 + 2048), n, dev, seed=31)
+    say(f"hilo beyond int32: T={T}")
+    got = ops.jacobi5_hilo(u0, T)
+    pts = sample_points(n, n, 24, seed=4) + [(n - 2, n // 2), (n // 2, n - 2), (46341, 46341)]
+    flat = torch.tensor([i * n + j for i, j in pts], dtype=torch.int64, device=dev)
+    vals = to_host(got.view(-1)[flat])
+    del got, u0
+    torch.cuda.empty_cache()
+    for k, (i, j) in enumerate(pts):
+        r0, r1, c0, c1 = cone_window(n, n, i, j, T)
+        m = oracle.jacobi5_hilo_model(hashed_grid(r0, r1 + 1, c0, c1 + 1, seed=31), T)
+        assert vals[k] == m[i - r0, j - c0], f"point {(i, j)}"
+
+
 def test_hilo_errors(ops):
     import torch
 
