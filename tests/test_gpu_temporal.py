@@ -142,3 +142,17 @@ def test_f32_full_size_default_schedule(ops):
     say("f32 4096 T=10 built-in schedule")
     got = to_host(ops.jacobi5(to_dev(u0), 10))
     assert np.array_equal(got, oracle.jacobi5(u0, 10, dtype=np.float32))
+
+
+@pytest.mark.parametrize("n,T", [(4096, 100), (8192, 25)], ids=["4096-T100", "8192-T25"])
+def test_f32_default_schedule_sampled(ops, n, T):
+    """FP32 through the plain call on sampled points, each from its dependence cone: 4096^2 at T = 100
+    (8 sweeps per launch: 100 sweeps split over 13 launches) and 8192^2 at T = 25 (one buffer past half
+    the MALL: 12 sweeps per launch, 25 split over 3 launches)."""
+    u0 = large_f64(0, n).astype(np.float32)
+    say(f"f32 {n} T={T} sampled (built-in)")
+    got = to_host(ops.jacobi5(to_dev(u0), T))
+    for (i, j) in sample_points(n, n, 24, seed=T):
+        r0, r1, c0, c1 = cone_window(n, n, i, j, T)
+        sub = oracle.jacobi5(u0[r0:r1 + 1, c0:c1 + 1], T, dtype=np.float32)
+        assert got[i, j] == sub[i - r0, j - c0], f"point {(i, j)}"
