@@ -209,6 +209,8 @@ def test_beyond_int32_points(ops, dtype):
             win = hashed_grid(r0, r1 + 1, c0, c1 + 1, seed=11).astype(dtype)
             sub = oracle.jacobi5(win, T, dtype=dtype)
             assert vals[k] == sub[i - r0, j - c0], f"T={T} point {(i, j)}"
+    del u0
+    torch.cuda.empty_cache()  # hand the 2^31-point buffers back before the next test
 
 
 def test_errors_reported(ops):
