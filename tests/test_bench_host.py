@@ -1,0 +1,38 @@
+"""Host logic of bench.py (no GPU): the traffic record's source check and the CPU-baseline sample."""
+
+import json
+
+import bench
+from workloads import normal_grid
+
+
+def _kernel_file(tmp_path, body):
+    p = tmp_path / "k.hip"
+    p.write_text("// header\n// BEGIN KERNEL SOURCE\n" + body + "// END KERNEL SOURCE\nint host_only;\n")
+    return str(p)
+
+
+def test_source_sha_ignores_comments_and_blank_lines(tmp_path):
+    a = _kernel_file(tmp_path, "int f(int x) {\n    return x + 1;  // one\n}\n")
+    sha = bench.source_sha(a)
+    b = _kernel_file(tmp_path, "int f(int x) {\n\n    return x + 1;    // another comment\n}\n")
+    assert bench.source_sha(b) == sha
+    c = _kernel_file(tmp_path, "int f(int x) {\n    return x + 2;\n}\n")
+    assert bench.source_sha(c) != sha
+
+
+def test_traffic_record_dropped_when_kernel_changes(tmp_path):
+    src = _kernel_file(tmp_path, "int f(int x) { return x; }\n")
+    rec = tmp_path / "traffic.json"
+    rec.write_text(json.dumps({"source_sha": bench.source_sha(src), "bytes_per_launch": 123.0}))
+    assert bench.load_traffic(str(rec), src) == 123.0
+    _kernel_file(tmp_path, "int f(int x) { return -x; }\n")  # same path, new code
+    assert bench.load_traffic(str(rec), src) is None
+    assert bench.load_traffic(str(tmp_path / "missing.json"), src) is None
+
+
+def test_cpu_baseline_sample():
+    r = bench.cpu_baseline(normal_grid(66, 130, seed=1), T_step=10, budget_s=0.2)
+    assert r["kind"] == "oracle" and r["unit"] == "GB/s"
+    assert r["cores"] >= 1 and r["value"] > 0
+    assert "sweeps in" in r["sample"] and "calls of" in r["sample"]
