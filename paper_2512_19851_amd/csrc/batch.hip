@@ -474,11 +474,28 @@ void build_descs(sten_batch_plan_s* p) {
     for (const Item& it : items) p->h_descs.push_back(it.d);
 }
 
+// A grid swept in global memory with T >= 2 ping-pongs through its `work`
+// buffer, so that buffer must exist. Which grids land in global mode depends
+// on the configuration (LDS budget, block, register mode), so this is checked
+// after every classification, before anything reaches the device.
+sten_status check_global_work(const sten_batch_plan_s* p) {
+    if (p->T < 2) return STEN_OK;
+    for (const Desc& d : p->h_descs)
+        if (d.mode == MODE_GLOBAL && (d.work == nullptr || !is_device_ptr(d.work))) return STEN_ERR_PTR;
+    return STEN_OK;
+}
+
+// Classify under p->cfg, check the classification and upload the descriptors.
+// On STEN_ERR_PTR nothing has been sent to the device: the previously
+// uploaded descriptors (if any) are unchanged, but h_descs and the class
+// counts describe the rejected configuration until the caller finalizes again.
 sten_status finalize_plan(sten_batch_plan_s* p, hipStream_t stream) {
     const int limit = device_lds_limit();
     p->cfg.lds_bytes = std::min(p->cfg.lds_bytes, limit);
     p->cfg.lds_bytes = std::max(p->cfg.lds_bytes, kStaticLds + 16);
     build_descs(p);
+    sten_status st = check_global_work(p);
+    if (st != STEN_OK) return st;
     p->grid = std::max(1, device_cus() * std::max(1, p->cfg.wg_per_cu));
     const size_t dyn = (size_t)(p->cfg.lds_bytes - kStaticLds);
     hipError_t e = hipFuncSetAttribute((const void*)batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -539,15 +556,7 @@ sten_status sten_batch_plan(const sten_inst* insts, int32_t count, int32_t T, fl
     Config cfg;
     if (!cache_lookup(tune_cache_path, batch_key(insts, count, T), cfg)) cfg = Config{};
     p->cfg = cfg;
-    // a grid that needs the second buffer in global memory must have one
-    build_descs(p);
-    for (const Desc& d : p->h_descs) {
-        if (d.mode == MODE_GLOBAL && T >= 2 && (d.work == nullptr || !is_device_ptr(d.work))) {
-            delete p;
-            return STEN_ERR_PTR;
-        }
-    }
-    st = finalize_plan(p, stream);
+    st = finalize_plan(p, stream);  // rejects a global-mode grid without `work` (T >= 2)
     if (st != STEN_OK) {
         delete p;
         return st;
@@ -648,7 +657,12 @@ sten_status sten_batch_autotune(sten_batch_handle plan, const char* tune_cache_p
     sten_status st = STEN_OK;
     for (const Config& cand : cands) {
         plan->cfg = cand;
-        if ((st = finalize_plan(plan, stream)) != STEN_OK) break;
+        st = finalize_plan(plan, stream);
+        if (st == STEN_ERR_PTR) {  // sends a grid without `work` to global mode: not a candidate
+            st = STEN_OK;
+            continue;
+        }
+        if (st != STEN_OK) break;
         if ((st = launch_plan(plan, stream)) != STEN_OK) break;  // warm-up
         if ((he = hipEventRecord(e0, stream)) != hipSuccess) { st = hip_fail(he); break; }
         for (int r = 0; r < reps && st == STEN_OK; ++r) st = launch_plan(plan, stream);

@@ -166,3 +166,25 @@ def test_batch_shapes_recipe():
     n = np.array([h * w for h, w in shapes])
     assert len(shapes) == 1024 and min(min(s) for s in shapes) >= 3
     assert n.min() >= 200 and n.max() <= 66000
+
+
+def test_reconfigure_rejects_global_grid_without_work(ops):
+    """A plan whose grids have no `work` buffer stays valid: any configuration that would
+    sweep such a grid in global memory (T >= 2) is refused with STEN_ERR_PTR, the plan keeps
+    its previous configuration, and the autotuner skips those candidates."""
+    shapes = [s for s in MIXED_SHAPES if s != (300, 250)]  # every grid fits registers or LDS by default
+    u0s = [normal_grid(*s, seed=40 + k, dtype=np.float32) for k, s in enumerate(shapes)]
+    plan = ops.BatchPlan([to_dev(u) for u in u0s], 3, works=[None] * len(u0s))
+    before = plan.info()
+    assert before["n_global"] == 0
+    say(f"batch no-work plan {before}")
+    with pytest.raises(RuntimeError, match="STEN_ERR_PTR|-3"):
+        plan.configure(64, 1024, 1)  # 1 KiB of LDS: the larger grids would sweep in global memory
+    assert plan.info() == before
+    with pytest.raises(RuntimeError, match="STEN_ERR_PTR|-3"):
+        plan.set_register_mode(False)  # 256 x 255 needs 510 KiB in LDS mode
+    assert plan.info() == before
+    _check(plan.run(), u0s, 3)
+    plan.autotune(None, reps=1)
+    assert plan.info()["n_global"] == 0
+    _check(plan.run(), u0s, 3)
