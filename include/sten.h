@@ -29,6 +29,11 @@
  *     input to the output (NumPy's empty-slice semantics). H == 0 or W == 0
  *     is a valid no-op.
  *   - Results are deterministic: the same inputs give the same bits.
+ *   - Tuning settings (sten_tune_*) are process-wide. Each is stored and read
+ *     atomically, and every value a setter accepts gives the same results
+ *     (they change speed only), so calls may run in several threads while a
+ *     setter runs: a call then uses some mix of the old and new settings and
+ *     still computes the method.
  */
 #ifndef STEN_H
 #define STEN_H
@@ -53,6 +58,35 @@ typedef enum {
 
 /* Human-readable name of a status code (static string, never NULL). */
 const char* sten_status_string(sten_status s);
+
+/*
+ * Operations whose caller-provided device workspace sten_workspace_bytes
+ * sizes. The backend works only on buffers its caller owns (the paper's data
+ * layout gives each chare its own arrays, Section III-C), so every call that
+ * needs scratch space takes it as an argument; this is the one query for how
+ * much.
+ */
+typedef enum {
+    STEN_OP_F64 = 0,    /* sten_jacobi5_f64: the `work` grid (FP64) */
+    STEN_OP_F32 = 1,    /* sten_jacobi5_f32: the `work` grid (FP32) */
+    STEN_OP_HILO = 2,   /* sten_jacobi5_f64_hilo: `work` (two encoded grids) */
+    STEN_OP_BATCH = 3,  /* sten_batch_plan: `dev_ws`, with H = number of grids (W, T ignored) */
+    STEN_OP_ADJ = 4,    /* sten_jacobi5_adjoint_f32: the `work` grid (FP32) */
+    STEN_OP_STATES = 5  /* sten_jacobi5_f32_states: the T + 1 recorded FP32 grids */
+} sten_op;
+
+/* Value sten_workspace_bytes returns for an unknown op or invalid sizes. */
+#define STEN_WORKSPACE_INVALID ((size_t)-1)
+
+/*
+ * Bytes of device workspace `op` needs on an H x W grid with row stride
+ * ld = W (a wider stride needs H * ld elements per grid instead) and T
+ * sweeps. 0 when the call needs none: T < 2 or an empty interior for the
+ * plain and adjoint grids, H == 0 or W == 0 otherwise. STEN_WORKSPACE_INVALID
+ * for an unknown op, H, W or T negative, H or W above 2^30, or a size past
+ * SIZE_MAX. Pure host function; no HIP call.
+ */
+size_t sten_workspace_bytes(int op, int64_t H, int64_t W, int32_t T);
 
 /* hipError_t of the most recent STEN_ERR_HIP returned on the calling thread. */
 int sten_last_hip_error(void);
@@ -136,7 +170,10 @@ sten_status sten_jacobi5_f32_tb(const float* u0, float* out, float* work, int64_
                                 int32_t T, float c, int32_t levels, hipStream_t stream);
 
 /* Tuning hook for the temporally blocked kernels. variant: 0 built-in
- * (streaming), 1 register tile, 2 streaming. band: output rows per streaming
+ * (streaming), 1 register tile (it has launches of 1..6 sweeps; launches of
+ * more sweeps, such as those of the plain calls' built-in schedule, still
+ * take the streaming kernel, and sten_jacobi5_*_tb accepts levels up to 12
+ * under either variant), 2 streaming. band: output rows per streaming
  * band (1..65536; 0 built-in: the tallest bands, in whole groups, that let
  * every resident wave slot hold one band). depth: rows the streaming kernel
  * loads ahead of the row it computes (0 or 4, the one depth built). Process-
@@ -162,8 +199,8 @@ sten_status sten_fill_rect_f64(double* grid, int64_t H, int64_t W, int64_t ld, i
 sten_status sten_tune_schedule(int32_t levels);
 
 /* Tuning hook: output rows per workgroup tile of the sweep kernels (4, 8 or
- * 16; 0 restores the built-in choice). Process-wide; not thread-safe against
- * concurrent launches. STEN_ERR_ARG for other values. */
+ * 16; 0 restores the built-in choice). Process-wide; same bits for every
+ * value. STEN_ERR_ARG for other values. */
 sten_status sten_tune_sweep_rows(int32_t rows);
 
 /* ------------------------------------------------------------------------ */

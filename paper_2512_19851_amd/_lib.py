@@ -17,6 +17,10 @@ import torch  # noqa: F401  (must precede loading libsten; see module docstring)
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsten.so")
 
+# sten_op values of include/sten.h
+OP_F64, OP_F32, OP_HILO, OP_BATCH, OP_ADJ, OP_STATES = range(6)
+WORKSPACE_INVALID = ctypes.c_size_t(-1).value
+
 STATUS = {
     0: "STEN_OK",
     -1: "STEN_ERR_ARG",
@@ -52,6 +56,7 @@ _f32 = ctypes.c_float
 SIGNATURES = {
     "sten_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "sten_last_hip_error": (ctypes.c_int, []),
+    "sten_workspace_bytes": (_sz, [ctypes.c_int, _i64, _i64, _i32]),
     "sten_version": (ctypes.c_char_p, []),
     "sten_xcd_tile_of_block": (_u32, [_u32, _u32]),
     "sten_jacobi5_f64": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, _i64, _i32, _f64, _vp]),

@@ -69,6 +69,29 @@ const char* sten_status_string(sten_status s) {
 
 int sten_last_hip_error(void) { return sten::g_last_hip_error; }
 
+size_t sten_workspace_bytes(int op, int64_t H, int64_t W, int32_t T) {
+    constexpr int64_t kMaxSide = (int64_t)1 << 30;
+    if (H < 0 || W < 0 || T < 0 || H > kMaxSide || W > kMaxSide) return STEN_WORKSPACE_INVALID;
+    const bool interior = H >= 3 && W >= 3;
+    const size_t points = (size_t)H * (size_t)W;  // below 2^60: no overflow
+    switch (op) {
+        case STEN_OP_F64: return (interior && T >= 2) ? points * sizeof(double) : 0;
+        case STEN_OP_F32:
+        case STEN_OP_ADJ: return (interior && T >= 2) ? points * sizeof(float) : 0;
+        case STEN_OP_HILO: return (H == 0 || W == 0) ? 0 : sten_jacobi5_f64_hilo_work_bytes(H, W);
+        case STEN_OP_BATCH:
+            return H > INT32_MAX ? STEN_WORKSPACE_INVALID : sten_batch_workspace_bytes((int32_t)H);
+        case STEN_OP_STATES: {
+            if (points == 0) return 0;
+            const size_t grids = (size_t)T + 1;
+            const size_t per = points * sizeof(float);
+            if (per > SIZE_MAX / grids) return STEN_WORKSPACE_INVALID;
+            return per * grids;
+        }
+        default: return STEN_WORKSPACE_INVALID;
+    }
+}
+
 uint32_t sten_xcd_tile_of_block(uint32_t b, uint32_t nb) { return sten::xcd_tile_of_block(b, nb); }
 
 const char* sten_version(void) { return "libsten 0.1 (gfx950)"; }

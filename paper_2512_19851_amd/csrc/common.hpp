@@ -69,6 +69,7 @@ struct GridView {
 // Streaming blocked kernel on several FP64 grids at once (temporal.hip), up to
 // kMaxStreamGridsPerLaunch grids per launch.
 constexpr int kMaxStreamGridsPerLaunch = 32;
-void launch_stream_grids_f64(const GridView<double>* views, int n, double c, int levels, hipStream_t s);
+// Returns false, with nothing launched, for levels outside 1..12.
+bool launch_stream_grids_f64(const GridView<double>* views, int n, double c, int levels, hipStream_t s);
 
 }  // namespace sten

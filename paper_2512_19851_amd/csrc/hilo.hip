@@ -24,6 +24,7 @@
 // vector and an 8-byte q vector per row) through registers, neighbours across
 // lanes come by shuffle, the wave's edge lanes load the one outside neighbour.
 #include <algorithm>
+#include <atomic>
 
 #include "common.hpp"
 
@@ -550,7 +551,9 @@ Coef make_coef(double c) {
     return k;
 }
 
-int g_hilo_variant = 0;
+// Process-wide variant setting, read atomically once per call; both variants
+// compute the same bits.
+std::atomic<int> g_hilo_variant{0};
 
 template <int V, int ROWS>
 void launch_hilo_rows(const Planes& in, const Planes& out, int H, int W, int64_t ld, const Coef& c, hipStream_t s) {
@@ -642,7 +645,8 @@ sten_status run_hilo_sweeps(const Planes& src, const Planes& dst, const Planes& 
     hilo_copy_kernel<<<grid_blocks(total), 256, 0, stream>>>(src.h, src.q, dst.h, dst.q,
                                                              need_work ? work.h : nullptr,
                                                              need_work ? work.q : nullptr, H, W, ld, 0);
-    const int variant = g_hilo_variant > 0 ? g_hilo_variant : kHiloDefaultVariant;
+    const int variant_set = g_hilo_variant.load(std::memory_order_relaxed);
+    const int variant = variant_set > 0 ? variant_set : kHiloDefaultVariant;
     Planes cur = src;
     for (int32_t k = 1; k <= T; ++k) {
         const Planes& d = ((T - k) % 2 == 0) ? dst : work;
@@ -726,7 +730,8 @@ sten_status sten_jacobi5_f64_hilo(const double* u0, double* out, void* work, siz
     Planes cur = a;
     if (T > 0 && H >= 3 && W >= 3) {
         const Coef k = make_coef(c);
-        const int variant = g_hilo_variant > 0 ? g_hilo_variant : kHiloDefaultVariant;
+        const int variant_set = g_hilo_variant.load(std::memory_order_relaxed);
+        const int variant = variant_set > 0 ? variant_set : kHiloDefaultVariant;
         for (int32_t s = 0; s < T; ++s) {
             const Planes& d = (s % 2 == 0) ? b : a;
             launch_hilo(cur, d, h, w, ld, k, variant, stream);

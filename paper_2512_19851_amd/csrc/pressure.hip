@@ -30,6 +30,7 @@
 // level is the same expression on the same operands, evaluated in the same
 // order, without contraction.
 #include <algorithm>
+#include <atomic>
 
 #include "common.hpp"
 #include "stream_common.hpp"
@@ -277,7 +278,9 @@ int resident_waves_of(const void* kernel) {
     return cus * per_cu;
 }
 
-int g_pressure_band = 0;  // tuning hook: rows per band (0: built-in)
+// Process-wide tuning setting, read atomically: rows per band (0: built-in).
+// Any band height gives the same results.
+std::atomic<int> g_pressure_band{0};
 
 template <int TL>
 void launch_pressure(const double* p, const double* b, double* out, int H, int W, int64_t ld, double cw, double cn,
@@ -285,7 +288,7 @@ void launch_pressure(const double* p, const double* b, double* out, int H, int W
     constexpr int HALO = (TL + kPV - 1) / kPV * kPV;
     constexpr int OW = 64 * kPV - 2 * HALO;
     const uint32_t strips = ceil_div(W - 64 * kPV, OW) + 1;
-    int band = g_pressure_band;
+    int band = g_pressure_band.load(std::memory_order_relaxed);
     if (band <= 0) {
         // the tallest bands that give every resident wave slot a band (one round), at least 2*TL rows
         static const int waves = resident_waves_of(reinterpret_cast<const void*>(&pressure_stream_kernel<TL>));

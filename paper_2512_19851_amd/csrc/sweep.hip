@@ -19,12 +19,13 @@
 //  * The arithmetic is exactly the listing's order with one rounding per
 //    operation; the library is built with -ffp-contract=off.
 #include <algorithm>
+#include <atomic>
 
 #include "common.hpp"
 
 namespace sten {
 
-void launch_levels_f64(const double* in, double* out, int H, int W, int64_t ld, double c, int levels,
+bool launch_levels_f64(const double* in, double* out, int H, int W, int64_t ld, double c, int levels,
                        hipStream_t s);
 sten_status run_tb_f64(const double* u0, double* out, double* work, int64_t H, int64_t W, int64_t ld, int32_t T,
                        double c, int32_t levels, hipStream_t stream);
@@ -218,8 +219,10 @@ __global__ void copy_kernel(const T* __restrict__ src, T* __restrict__ dst, int 
     }
 }
 
-int g_rows_override = 0;  // 0: built-in choice; else rows per tile (tuning hook)
-int g_schedule = 0;       // sweeps per launch of the plain calls: 0 built-in (temporal blocking), 1 single
+// Process-wide tuning settings, read atomically; every accepted value gives
+// the same results, so a call racing a setter still computes the method.
+std::atomic<int> g_rows_override{0};  // 0: built-in choice; else rows per tile
+std::atomic<int> g_schedule{0};       // sweeps per launch of the plain calls: 0 built-in (temporal blocking), 1 single
 
 // Most sweeps per launch the plain calls use when the grid allows temporal
 // blocking; the T sweeps are split evenly over ceil(T / levels) launches.
@@ -268,7 +271,8 @@ sten_status run_jacobi5(const T* u0, T* out, T* work, int64_t H, int64_t W, int6
     if (st != STEN_OK || H == 0 || W == 0) return st;
     const int h = (int)H, w = (int)W;
     constexpr int VT = 16 / (int)sizeof(T);
-    const int levels = g_schedule == 0 ? default_levels<T>(H, W) : g_schedule;
+    const int sched = g_schedule.load(std::memory_order_relaxed);
+    const int levels = sched == 0 ? default_levels<T>(H, W) : sched;
     if (interior && levels > 1 && T_ >= 2 &&
         ((((uintptr_t)u0 | (uintptr_t)out | (uintptr_t)work) % 16) == 0) && ld % VT == 0) {
         // same bits, fewer passes over HBM: several sweeps per launch
@@ -288,7 +292,8 @@ sten_status run_jacobi5(const T* u0, T* out, T* work, int64_t H, int64_t W, int6
     constexpr int VV = 16 / (int)sizeof(T);
     const uintptr_t align_bits = (uintptr_t)u0 | (uintptr_t)out | (need_work ? (uintptr_t)work : 0);
     const bool vec_ok = (align_bits % 16 == 0) && (ld % VV == 0);
-    const int rows = g_rows_override > 0 ? g_rows_override : 4;
+    const int rows_set = g_rows_override.load(std::memory_order_relaxed);
+    const int rows = rows_set > 0 ? rows_set : 4;
     const T* src = u0;
     for (int32_t k = 1; k <= T_; ++k) {
         T* dst = ((T_ - k) % 2 == 0) ? out : work;
@@ -307,7 +312,8 @@ sten_status run_sweep_once(const T* src, T* dst, int64_t H, int64_t W, int64_t l
     if (st != STEN_OK || H < 3 || W < 3) return st;
     constexpr int VV = 16 / (int)sizeof(T);
     const bool vec_ok = (((uintptr_t)src | (uintptr_t)dst) % 16 == 0) && (ld % VV == 0);
-    const int rows = g_rows_override > 0 ? g_rows_override : 4;
+    const int rows_set = g_rows_override.load(std::memory_order_relaxed);
+    const int rows = rows_set > 0 ? rows_set : 4;
     if (vec_ok)
         launch_sweep<T, VV>(src, dst, (int)H, (int)W, ld, c, rows, stream);
     else
@@ -332,7 +338,8 @@ sten_status run_chain_f64(double* a, double* b, int64_t H, int64_t W, int64_t ld
     if (overlaps(a, span, b, span)) return STEN_ERR_ALIAS;
     if (!is_device_ptr(a) || !is_device_ptr(b)) return STEN_ERR_PTR;
     const int h = (int)H, w = (int)W;
-    const int L = g_schedule == 0 ? default_levels<double>(H, W) : g_schedule;
+    const int sched = g_schedule.load(std::memory_order_relaxed);
+    const int L = sched == 0 ? default_levels<double>(H, W) : sched;
     const bool blocked = L > 1 && (((uintptr_t)a | (uintptr_t)b) % 16) == 0 && ld % 2 == 0 &&
                          W * (int64_t)sizeof(double) < ((int64_t)1 << 30);
     const int n = m - 1;  // sweeps before the last one
@@ -348,8 +355,8 @@ sten_status run_chain_f64(double* a, double* b, int64_t H, int64_t W, int64_t ld
             const int lev = base + (j <= extra ? 1 : 0);
             if (lev == 1)
                 launch_sweep_f64_internal(src, dst, h, w, ld, c, stream);
-            else
-                launch_levels_f64(src, dst, h, w, ld, c, lev, stream);
+            else if (!launch_levels_f64(src, dst, h, w, ld, c, lev, stream))
+                return STEN_ERR_ARG;  // unreachable: 2 <= lev <= L <= 12 and the rows fit the streaming kernel
             src = dst;
         }
     } else {
@@ -366,7 +373,8 @@ sten_status run_chain_f64(double* a, double* b, int64_t H, int64_t W, int64_t ld
 // FP64 sweep launch for other parts of the library (no argument checks).
 void launch_sweep_f64_internal(const double* in, double* out, int H, int W, int64_t ld, double c, hipStream_t s) {
     const bool vec_ok = (((uintptr_t)in | (uintptr_t)out) % 16 == 0) && (ld % 2 == 0);
-    const int rows = g_rows_override > 0 ? g_rows_override : 4;
+    const int rows_set = g_rows_override.load(std::memory_order_relaxed);
+    const int rows = rows_set > 0 ? rows_set : 4;
     if (vec_ok)
         launch_sweep<double, 2>(in, out, H, W, ld, c, rows, s);
     else
@@ -376,7 +384,8 @@ void launch_sweep_f64_internal(const double* in, double* out, int H, int W, int6
 // FP32 sweep launch for other parts of the library (no argument checks).
 void launch_sweep_f32_internal(const float* in, float* out, int H, int W, int64_t ld, float c, hipStream_t s) {
     const bool vec_ok = (((uintptr_t)in | (uintptr_t)out) % 16 == 0) && (ld % 4 == 0);
-    const int rows = g_rows_override > 0 ? g_rows_override : 4;
+    const int rows_set = g_rows_override.load(std::memory_order_relaxed);
+    const int rows = rows_set > 0 ? rows_set : 4;
     if (vec_ok)
         launch_sweep<float, 4>(in, out, H, W, ld, c, rows, s);
     else

@@ -18,6 +18,7 @@
 // of recomputing the halo (rows: 2*TL per ROWS, columns: 2*TL per 64*V) and
 // re-reading halo rows from L2.
 #include <algorithm>
+#include <atomic>
 
 #include "common.hpp"
 #include "stream_common.hpp"
@@ -435,35 +436,40 @@ void launch_tb(const T* in, T* out, int H, int W, int64_t ld, T c, hipStream_t s
     sweep_tb_kernel<T, V, ROWS, TL><<<strips * bands, 64, 0, s>>>(in, out, H, W, ld, c, strips);
 }
 
-int g_tb_rows = 0;     // tuning hook: output rows per register tile (0: 8)
-int g_tb_variant = 0;  // 0: built-in (streaming), 1: register tile, 2: streaming
-int g_tb_band = 0;     // streaming: output rows per band (0: built-in)
-int g_tb_depth = 0;    // streaming: rows loaded ahead (0 or 4; loading 7 ahead measured no faster)
+// Process-wide tuning settings. Each is read atomically wherever a launch is
+// configured, and every value a setter accepts gives the same results, so a
+// call racing a setter runs some valid mix of old and new settings.
+std::atomic<int> g_tb_rows{0};     // output rows per register tile (0: 8)
+std::atomic<int> g_tb_variant{0};  // 0: built-in (streaming), 1: register tile where it has the level count, 2: streaming
+std::atomic<int> g_tb_band{0};     // streaming: output rows per band (0: built-in)
+std::atomic<int> g_tb_depth{0};    // streaming: rows loaded ahead (0 or 4; loading 7 ahead measured no faster)
 
 constexpr int kStreamDepth = 4;
 constexpr int kMaxBlockLevels = 6;
 constexpr int kMaxStreamLevels = 12;
 
+// false (nothing launched) for a level count without a kernel
 template <typename T, int V, int ROWS>
-void launch_levels_rows(const T* in, T* out, int H, int W, int64_t ld, T c, int levels, hipStream_t s) {
+bool launch_levels_rows(const T* in, T* out, int H, int W, int64_t ld, T c, int levels, hipStream_t s) {
     switch (levels) {
-        case 1: launch_tb<T, V, ROWS, 1>(in, out, H, W, ld, c, s); break;
-        case 2: launch_tb<T, V, ROWS, 2>(in, out, H, W, ld, c, s); break;
-        case 3: launch_tb<T, V, ROWS, 3>(in, out, H, W, ld, c, s); break;
-        case 4: launch_tb<T, V, ROWS, 4>(in, out, H, W, ld, c, s); break;
-        case 5: launch_tb<T, V, ROWS, 5>(in, out, H, W, ld, c, s); break;
-        default: launch_tb<T, V, ROWS, 6>(in, out, H, W, ld, c, s); break;
+        case 1: launch_tb<T, V, ROWS, 1>(in, out, H, W, ld, c, s); return true;
+        case 2: launch_tb<T, V, ROWS, 2>(in, out, H, W, ld, c, s); return true;
+        case 3: launch_tb<T, V, ROWS, 3>(in, out, H, W, ld, c, s); return true;
+        case 4: launch_tb<T, V, ROWS, 4>(in, out, H, W, ld, c, s); return true;
+        case 5: launch_tb<T, V, ROWS, 5>(in, out, H, W, ld, c, s); return true;
+        case 6: launch_tb<T, V, ROWS, 6>(in, out, H, W, ld, c, s); return true;
+        default: return false;
     }
 }
 
 // One register-tile launch of `levels` sweeps (1..6).
 template <typename T, int V>
-void launch_levels_block(const T* in, T* out, int H, int W, int64_t ld, T c, int levels, hipStream_t s) {
-    switch (g_tb_rows) {
-        case 4: launch_levels_rows<T, V, 4>(in, out, H, W, ld, c, levels, s); break;
-        case 12: launch_levels_rows<T, V, 12>(in, out, H, W, ld, c, levels, s); break;
-        case 16: launch_levels_rows<T, V, 16>(in, out, H, W, ld, c, levels, s); break;
-        default: launch_levels_rows<T, V, 8>(in, out, H, W, ld, c, levels, s); break;
+bool launch_levels_block(const T* in, T* out, int H, int W, int64_t ld, T c, int levels, hipStream_t s) {
+    switch (g_tb_rows.load(std::memory_order_relaxed)) {
+        case 4: return launch_levels_rows<T, V, 4>(in, out, H, W, ld, c, levels, s);
+        case 12: return launch_levels_rows<T, V, 12>(in, out, H, W, ld, c, levels, s);
+        case 16: return launch_levels_rows<T, V, 16>(in, out, H, W, ld, c, levels, s);
+        default: return launch_levels_rows<T, V, 8>(in, out, H, W, ld, c, levels, s);
     }
 }
 
@@ -485,7 +491,7 @@ void launch_stream(const T* in, T* out, int H, int W, int64_t ld, T c, hipStream
     // flush: enough regular strips that the last (right-aligned) strip meets them; else strip k
     // stores columns [k*OW, (k+1)*OW)
     const uint32_t strips = flush ? ceil_div(W - 64 * V, OW) + 1 : ceil_div(W - 1, OW);
-    int band = g_tb_band;
+    int band = g_tb_band.load(std::memory_order_relaxed);
     if (band <= 0) {
         // Built-in: the tallest bands that still give every resident wave slot
         // a band, so the grid runs in one round; at least 2*TL rows, so a band
@@ -499,20 +505,21 @@ void launch_stream(const T* in, T* out, int H, int W, int64_t ld, T c, hipStream
 }
 
 template <typename T, int V, int D>
-void launch_stream_depth(const T* in, T* out, int H, int W, int64_t ld, T c, int levels, hipStream_t s) {
+bool launch_stream_depth(const T* in, T* out, int H, int W, int64_t ld, T c, int levels, hipStream_t s) {
     switch (levels) {
-        case 1: launch_stream<T, V, 1, D>(in, out, H, W, ld, c, s); break;
-        case 2: launch_stream<T, V, 2, D>(in, out, H, W, ld, c, s); break;
-        case 3: launch_stream<T, V, 3, D>(in, out, H, W, ld, c, s); break;
-        case 4: launch_stream<T, V, 4, D>(in, out, H, W, ld, c, s); break;
-        case 5: launch_stream<T, V, 5, D>(in, out, H, W, ld, c, s); break;
-        case 6: launch_stream<T, V, 6, D>(in, out, H, W, ld, c, s); break;
-        case 7: launch_stream<T, V, 7, D>(in, out, H, W, ld, c, s); break;
-        case 8: launch_stream<T, V, 8, D>(in, out, H, W, ld, c, s); break;
-        case 9: launch_stream<T, V, 9, D>(in, out, H, W, ld, c, s); break;
-        case 10: launch_stream<T, V, 10, D>(in, out, H, W, ld, c, s); break;
-        case 11: launch_stream<T, V, 11, D>(in, out, H, W, ld, c, s); break;
-        default: launch_stream<T, V, 12, D>(in, out, H, W, ld, c, s); break;
+        case 1: launch_stream<T, V, 1, D>(in, out, H, W, ld, c, s); return true;
+        case 2: launch_stream<T, V, 2, D>(in, out, H, W, ld, c, s); return true;
+        case 3: launch_stream<T, V, 3, D>(in, out, H, W, ld, c, s); return true;
+        case 4: launch_stream<T, V, 4, D>(in, out, H, W, ld, c, s); return true;
+        case 5: launch_stream<T, V, 5, D>(in, out, H, W, ld, c, s); return true;
+        case 6: launch_stream<T, V, 6, D>(in, out, H, W, ld, c, s); return true;
+        case 7: launch_stream<T, V, 7, D>(in, out, H, W, ld, c, s); return true;
+        case 8: launch_stream<T, V, 8, D>(in, out, H, W, ld, c, s); return true;
+        case 9: launch_stream<T, V, 9, D>(in, out, H, W, ld, c, s); return true;
+        case 10: launch_stream<T, V, 10, D>(in, out, H, W, ld, c, s); return true;
+        case 11: launch_stream<T, V, 11, D>(in, out, H, W, ld, c, s); return true;
+        case 12: launch_stream<T, V, 12, D>(in, out, H, W, ld, c, s); return true;
+        default: return false;
     }
 }
 
@@ -541,9 +548,10 @@ void launch_stream_grids(const GridView<T>* views, int n, T c, hipStream_t s) {
         resident_waves(reinterpret_cast<const void*>(&sweep_stream_grids_kernel<T, V, TL, D>));
     const int64_t fit = std::max<int64_t>(1, (waves > 0 ? waves : 1024) / std::max<int64_t>(1, all_strips));
     uint32_t first = 0;
+    const int band_set = g_tb_band.load(std::memory_order_relaxed);
     for (int k = 0; k < n; ++k) {
         StreamGrid<T>& g = args.g[k];
-        g.band = g_tb_band > 0 ? g_tb_band : (int)std::max<int64_t>(2 * TL, (g.H - 2 + fit - 1) / fit);
+        g.band = band_set > 0 ? band_set : (int)std::max<int64_t>(2 * TL, (g.H - 2 + fit - 1) / fit);
         g.first = first;
         first += g.strips * ceil_div(g.H - 2, g.band);
     }
@@ -551,37 +559,42 @@ void launch_stream_grids(const GridView<T>* views, int n, T c, hipStream_t s) {
 }
 
 template <typename T, int V, int D>
-void launch_stream_grids_depth(const GridView<T>* views, int n, T c, int levels, hipStream_t s) {
+bool launch_stream_grids_depth(const GridView<T>* views, int n, T c, int levels, hipStream_t s) {
     switch (levels) {
-        case 1: launch_stream_grids<T, V, 1, D>(views, n, c, s); break;
-        case 2: launch_stream_grids<T, V, 2, D>(views, n, c, s); break;
-        case 3: launch_stream_grids<T, V, 3, D>(views, n, c, s); break;
-        case 4: launch_stream_grids<T, V, 4, D>(views, n, c, s); break;
-        case 5: launch_stream_grids<T, V, 5, D>(views, n, c, s); break;
-        case 6: launch_stream_grids<T, V, 6, D>(views, n, c, s); break;
-        case 7: launch_stream_grids<T, V, 7, D>(views, n, c, s); break;
-        case 8: launch_stream_grids<T, V, 8, D>(views, n, c, s); break;
-        case 9: launch_stream_grids<T, V, 9, D>(views, n, c, s); break;
-        case 10: launch_stream_grids<T, V, 10, D>(views, n, c, s); break;
-        case 11: launch_stream_grids<T, V, 11, D>(views, n, c, s); break;
-        default: launch_stream_grids<T, V, 12, D>(views, n, c, s); break;
+        case 1: launch_stream_grids<T, V, 1, D>(views, n, c, s); return true;
+        case 2: launch_stream_grids<T, V, 2, D>(views, n, c, s); return true;
+        case 3: launch_stream_grids<T, V, 3, D>(views, n, c, s); return true;
+        case 4: launch_stream_grids<T, V, 4, D>(views, n, c, s); return true;
+        case 5: launch_stream_grids<T, V, 5, D>(views, n, c, s); return true;
+        case 6: launch_stream_grids<T, V, 6, D>(views, n, c, s); return true;
+        case 7: launch_stream_grids<T, V, 7, D>(views, n, c, s); return true;
+        case 8: launch_stream_grids<T, V, 8, D>(views, n, c, s); return true;
+        case 9: launch_stream_grids<T, V, 9, D>(views, n, c, s); return true;
+        case 10: launch_stream_grids<T, V, 10, D>(views, n, c, s); return true;
+        case 11: launch_stream_grids<T, V, 11, D>(views, n, c, s); return true;
+        case 12: launch_stream_grids<T, V, 12, D>(views, n, c, s); return true;
+        default: return false;
     }
 }
 
-// One blocked launch of `levels` sweeps.
+// One blocked launch of `levels` sweeps (1..12). The register tile has 1..6
+// levels: it runs when asked for (variant 1) or when rows are too wide for
+// the streaming kernel, and only for a level count it has. Returns false, with
+// nothing launched, for a level count no kernel has (wide rows: above 6).
 template <typename T, int V>
-void launch_levels(const T* in, T* out, int H, int W, int64_t ld, T c, int levels, hipStream_t s) {
+bool launch_levels(const T* in, T* out, int H, int W, int64_t ld, T c, int levels, hipStream_t s) {
     // the streaming kernel addresses a row with 32-bit byte offsets
     const bool stream_fits = (int64_t)W * (int64_t)sizeof(T) < ((int64_t)1 << 30);
-    if (g_tb_variant == 1 || (!stream_fits && levels <= kMaxBlockLevels))
+    if (levels <= kMaxBlockLevels && (!stream_fits || g_tb_variant.load(std::memory_order_relaxed) == 1))
         return launch_levels_block<T, V>(in, out, H, W, ld, c, levels, s);
-    launch_stream_depth<T, V, kStreamDepth>(in, out, H, W, ld, c, levels, s);
+    if (!stream_fits) return false;
+    return launch_stream_depth<T, V, kStreamDepth>(in, out, H, W, ld, c, levels, s);
 }
 
 template <typename T>
 sten_status run_tb(const T* u0, T* out, T* work, int64_t H, int64_t W, int64_t ld, int32_t T_, T c, int32_t tl,
                    hipStream_t stream) {
-    if (tl < 1 || tl > (g_tb_variant == 1 ? kMaxBlockLevels : kMaxStreamLevels)) return STEN_ERR_ARG;
+    if (tl < 1 || tl > kMaxStreamLevels) return STEN_ERR_ARG;
     // rows too wide for the streaming kernel's 32-bit offsets take the register tile
     if (W * (int64_t)sizeof(T) >= ((int64_t)1 << 30)) tl = std::min(tl, kMaxBlockLevels);
     const bool interior = H >= 3 && W >= 3;
@@ -603,7 +616,7 @@ sten_status run_tb(const T* u0, T* out, T* work, int64_t H, int64_t W, int64_t l
     for (int k = 1; k <= launches; ++k) {
         const int lev = base + (k <= extra ? 1 : 0);
         T* dst = ((launches - k) % 2 == 0) ? out : work;
-        launch_levels<T, VV>(src, dst, h, w, ld, c, lev, stream);
+        if (!launch_levels<T, VV>(src, dst, h, w, ld, c, lev, stream)) return STEN_ERR_ARG;  // unreachable: lev <= tl
         src = dst;
     }
     return check_launch();
@@ -614,17 +627,21 @@ sten_status run_tb(const T* u0, T* out, T* work, int64_t H, int64_t W, int64_t l
 // `levels` sweeps (1..12) on each of n independent grids, in launches of up to
 // kMaxStreamGrids grids. Each grid: H, W >= 3, in and out 16-byte aligned, ld
 // even and W * 8 below 2^30 bytes; the caller checks these.
-void launch_stream_grids_f64(const GridView<double>* views, int n, double c, int levels, hipStream_t s) {
+// Returns false, with nothing launched, for levels outside 1..12.
+bool launch_stream_grids_f64(const GridView<double>* views, int n, double c, int levels, hipStream_t s) {
+    if (levels < 1 || levels > kMaxStreamLevels) return false;
     for (int k = 0; k < n; k += kMaxStreamGrids)
         launch_stream_grids_depth<double, 2, kStreamDepth>(views + k, std::min(n - k, kMaxStreamGrids), c, levels,
                                                            s);
+    return true;
 }
 
 // One blocked launch of `levels` sweeps (1..12) from in to out, FP64 (no
-// argument checks; 16-byte aligned data, even ld, rows below 2^27 elements).
-void launch_levels_f64(const double* in, double* out, int H, int W, int64_t ld, double c, int levels,
+// argument checks; 16-byte aligned data, even ld). Returns false, with
+// nothing launched, for a level count no kernel has.
+bool launch_levels_f64(const double* in, double* out, int H, int W, int64_t ld, double c, int levels,
                        hipStream_t s) {
-    launch_levels<double, 2>(in, out, H, W, ld, c, levels, s);
+    return launch_levels<double, 2>(in, out, H, W, ld, c, levels, s);
 }
 
 // Entry used by the plain calls when they pick the blocked schedule.

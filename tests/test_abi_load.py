@@ -222,3 +222,43 @@ def test_expr_run_rejects_before_any_hip_call(lib):
     outs[0].base = 0x20000000
     assert run(b"L0,0,0", 0, 4) == 0                      # empty region
     assert b"expression" in lib.sten_expr_log() or lib.sten_expr_log() == b""
+
+
+def test_workspace_query_per_op(lib):
+    """sten_workspace_bytes agrees with each op's own query and with the buffers the calls take."""
+    from paper_2512_19851_amd import _lib
+
+    q = lib.sten_workspace_bytes
+    bad = _lib.WORKSPACE_INVALID
+    H, W = 4096, 4096
+    assert q(_lib.OP_F64, H, W, 100) == H * W * 8
+    assert q(_lib.OP_F32, H, W, 100) == H * W * 4
+    assert q(_lib.OP_ADJ, 1024, 1024, 10) == 1024 * 1024 * 4
+    assert q(_lib.OP_HILO, H, W, 100) == lib.sten_jacobi5_f64_hilo_work_bytes(H, W)
+    assert q(_lib.OP_HILO, H, W, 0) == lib.sten_jacobi5_f64_hilo_work_bytes(H, W)  # encode/decode staging
+    assert q(_lib.OP_BATCH, 1024, 0, 0) == lib.sten_batch_workspace_bytes(1024)
+    assert q(_lib.OP_STATES, 1024, 1024, 10) == 11 * 1024 * 1024 * 4
+    # no second buffer: T < 2 or an empty interior
+    for op in (_lib.OP_F64, _lib.OP_F32, _lib.OP_ADJ):
+        assert q(op, H, W, 0) == 0 and q(op, H, W, 1) == 0
+        assert q(op, 2, W, 10) == 0 and q(op, H, 2, 10) == 0
+    assert q(_lib.OP_HILO, 0, W, 3) == 0 and q(_lib.OP_STATES, H, 0, 3) == 0
+    assert q(_lib.OP_BATCH, 0, 0, 0) == lib.sten_batch_workspace_bytes(0)
+
+
+def test_workspace_query_errors(lib):
+    from paper_2512_19851_amd import _lib
+
+    q = lib.sten_workspace_bytes
+    bad = _lib.WORKSPACE_INVALID
+    assert bad == 2**64 - 1
+    for op in (-1, 6, 99):
+        assert q(op, 64, 64, 2) == bad  # unknown op
+    for op in range(6):
+        assert q(op, -1, 64, 2) == bad
+        assert q(op, 64, -1, 2) == bad
+        assert q(op, 64, 64, -1) == bad
+        assert q(op, (1 << 30) + 1, 64, 2) == bad
+    assert q(_lib.OP_BATCH, 2**31, 0, 0) == bad
+    # 2^30 x 2^30 FP32 states x (2^31) grids overflow size_t
+    assert q(_lib.OP_STATES, 1 << 30, 1 << 30, 2**31 - 1) == bad

@@ -156,3 +156,31 @@ def test_f32_default_schedule_sampled(ops, n, T):
         r0, r1, c0, c1 = cone_window(n, n, i, j, T)
         sub = oracle.jacobi5(u0[r0:r1 + 1, c0:c1 + 1], T, dtype=np.float32)
         assert got[i, j] == sub[i - r0, j - c0], f"point {(i, j)}"
+
+
+def test_register_variant_keeps_other_calls_whole(ops):
+    """With the register-tile variant selected (it has launches of 1..6 sweeps), the plain calls'
+    built-in schedule (up to 12 sweeps per launch) and the listing's chain of sweeps on two arrays
+    still apply every sweep: launches of more than 6 sweeps take the streaming kernel."""
+    import torch
+
+    from paper_2512_19851_amd import _lib
+
+    u0 = normal_grid(70, 300, seed=3)
+    f32 = u0.astype(np.float32)
+    try:
+        ops.set_tb(BLOCK, 0, 0)
+        for T in (6, 7, 12, 25, 100):
+            say(f"register variant: jacobi5 default schedule T={T}")
+            assert np.array_equal(to_host(ops.jacobi5(to_dev(u0), T)), oracle.jacobi5(u0, T)), f"f64 T={T}"
+            assert np.array_equal(to_host(ops.jacobi5(to_dev(f32), T)), oracle.jacobi5(f32, T, dtype=np.float32))
+        for m in (2, 8, 14, 27):
+            a, b = to_dev(u0), to_dev(u0)  # equal rings, as the chain requires
+            say(f"register variant: sweep chain m={m}")
+            _lib.call("sten_sweep_chain_f64", a.data_ptr(), b.data_ptr(), 70, 300, 300, m, 0.25,
+                      torch.cuda.current_stream().cuda_stream)
+            last, prev = (b, a) if m % 2 else (a, b)
+            assert np.array_equal(to_host(last), oracle.jacobi5(u0, m)), f"chain m={m}"
+            assert np.array_equal(to_host(prev), oracle.jacobi5(u0, m - 1)), f"chain m={m} previous iterate"
+    finally:
+        ops.set_tb(0, 0, 0)
