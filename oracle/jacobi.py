@@ -43,6 +43,7 @@ __all__ = [
     "gamma",
     "bound_fp32",
     "bound_adjoint_fp32",
+    "bound_hilo_from_abs",
     "bound_grad_c_fp32",
     "hilo_delta",
     "hilo_encode",
@@ -314,11 +315,16 @@ def bound_hilo(u0, T: int, c=0.25) -> np.ndarray:
     |err| <= ((T + 1) 2^-40 (1 + 2^-22) + T a) (1 + 2^-39)^T (|J| |u0|), a as above,
     plus an absolute term for values whose quantum is floored at 2^-149.
     """
+    return bound_hilo_from_abs(abs_reference(u0, T, c), T, c)
+
+
+def bound_hilo_from_abs(absref, T: int, c=0.25) -> np.ndarray:
+    """bound_hilo given |J| |u0| (abs_reference) computed elsewhere, e.g. by the C twin."""
     cf = float(c)
     m, _ = np.frexp(abs(cf))
     a = 17 * 2.0 ** -48 if (cf != 0.0 and m == 0.5) else 20 * 2.0 ** -48
     per = (T + 1) * 2.0 ** -40 * (1.0 + 2.0 ** -22) + T * a
-    return per * (1.0 + 2.0 ** -39) ** T * abs_reference(u0, T, c) + (T + 1) * 2.0 ** -149
+    return per * (1.0 + 2.0 ** -39) ** T * np.asarray(absref, dtype=np.float64) + (T + 1) * 2.0 ** -149
 
 
 # ---------------------------------------------------------------------------

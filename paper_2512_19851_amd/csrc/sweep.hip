@@ -207,6 +207,49 @@ __global__ void fill_rect_kernel(double* __restrict__ p, int64_t ld, int r0, int
     }
 }
 
+// Streaming copy of n16 16-byte units between 16-byte aligned buffers (a
+// contiguous grid, ld == W): every lane issues kCopyUnroll 16-byte loads, a
+// whole workgroup width apart so each wave's accesses stay coalesced, before
+// its stores. Units past the last whole pass go one at a time.
+constexpr int kCopyUnroll = 4;
+constexpr int kCopyBlock = 256;
+__global__ __launch_bounds__(kCopyBlock) void copy16_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                            int64_t n16) {
+    const int64_t base = (int64_t)blockIdx.x * (kCopyBlock * kCopyUnroll) + threadIdx.x;
+    if (base + (int64_t)(kCopyUnroll - 1) * kCopyBlock < n16) {
+        uint4 v[kCopyUnroll];
+#pragma unroll
+        for (int k = 0; k < kCopyUnroll; ++k) v[k] = src[base + k * kCopyBlock];
+#pragma unroll
+        for (int k = 0; k < kCopyUnroll; ++k) dst[base + k * kCopyBlock] = v[k];
+    } else {
+        for (int k = 0; k < kCopyUnroll; ++k)
+            if (base + k * kCopyBlock < n16) dst[base + k * kCopyBlock] = src[base + k * kCopyBlock];
+    }
+}
+
+// Bytes past the last whole 16-byte unit of a contiguous copy.
+__global__ void copy_tail_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst, int n) {
+    if ((int)threadIdx.x < n) dst[threadIdx.x] = src[threadIdx.x];
+}
+
+// Copy `bytes` contiguous bytes (both pointers 16-byte aligned).
+void launch_copy_contiguous(const void* src, void* dst, int64_t bytes, hipStream_t s) {
+    const int64_t n16 = bytes / 16;
+    // launches of at most 2^20 workgroups (16 GiB each), far inside the 32-bit work-item count
+    constexpr int64_t kChunk = ((int64_t)1 << 20) * kCopyBlock * kCopyUnroll;
+    for (int64_t off = 0; off < n16; off += kChunk) {
+        const int64_t n = std::min(kChunk, n16 - off);
+        const int64_t blocks = (n + kCopyBlock * kCopyUnroll - 1) / (kCopyBlock * kCopyUnroll);
+        copy16_kernel<<<(uint32_t)blocks, kCopyBlock, 0, s>>>(static_cast<const uint4*>(src) + off,
+                                                              static_cast<uint4*>(dst) + off, n);
+    }
+    const int tail = (int)(bytes - n16 * 16);
+    if (tail > 0)
+        copy_tail_kernel<<<1, 64, 0, s>>>(static_cast<const unsigned char*>(src) + n16 * 16,
+                                          static_cast<unsigned char*>(dst) + n16 * 16, tail);
+}
+
 // Plain 2-D copy of an H x W grid (degenerate calls: T = 0 or empty interior).
 template <typename T>
 __global__ void copy_kernel(const T* __restrict__ src, T* __restrict__ dst, int H, int W, int64_t ld) {
@@ -280,8 +323,12 @@ sten_status run_jacobi5(const T* u0, T* out, T* work, int64_t H, int64_t W, int6
     }
     if (!interior || T_ == 0) {
         const int64_t total = H * W;
-        const uint32_t blocks = (uint32_t)std::min<int64_t>((total + 255) / 256, 65536);
-        copy_kernel<T><<<blocks, 256, 0, stream>>>(u0, out, h, w, ld);
+        if ((ld == W || H == 1) && (((uintptr_t)u0 | (uintptr_t)out) % 16) == 0) {
+            launch_copy_contiguous(u0, out, total * (int64_t)sizeof(T), stream);
+        } else {
+            const uint32_t blocks = (uint32_t)std::min<int64_t>((total + 255) / 256, 65536);
+            copy_kernel<T><<<blocks, 256, 0, stream>>>(u0, out, h, w, ld);
+        }
         return check_launch();
     }
     {

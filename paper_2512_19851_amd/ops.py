@@ -194,11 +194,13 @@ def hilo_empty(H: int, W: int, ld: int | None = None, device=None) -> HiLoGrid:
     return HiLoGrid(buf, H, W, ld)
 
 
-def hilo_encode(x: torch.Tensor, stream=None) -> HiLoGrid:
-    """FP64 grid -> encoded grid (hi = RN32(x), q = rint((x - hi) / delta(hi)))."""
+def hilo_encode(x: torch.Tensor, out: HiLoGrid | None = None, stream=None) -> HiLoGrid:
+    """FP64 grid -> encoded grid (hi = RN32(x), q = rint((x - hi) / delta(hi))), into `out` when given."""
     _check_grid(x, torch.float64, "x")
     H, W = x.shape
-    g = hilo_empty(H, W, _ld(x), x.device)
+    g = out if out is not None else hilo_empty(H, W, _ld(x), x.device)
+    if (g.H, g.W, g.ld) != (H, W, _ld(x)):
+        raise ValueError("out must be an encoded grid of x's shape and row stride")
     _lib.call("sten_hilo_encode", x.data_ptr(), g.buf.data_ptr(), H, W, g.ld, _stream_ptr(stream))
     return g
 

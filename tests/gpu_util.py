@@ -46,14 +46,44 @@ def cone_window(H: int, W: int, i: int, j: int, T: int):
     return r0, r1, c0, c1
 
 
-def sample_points(H: int, W: int, n: int, seed: int = 0):
-    """Corners, ring points, tile-edge points and random interior points."""
+def stream_edges(H: int, W: int, V: int = 2, TL: int = 11, bands=(54, 22)):
+    """Store boundaries of the streaming blocked kernel: the first stored column of each strip (and the
+    column before it) in the right-aligned layout used when W is a multiple of V and at least 64*V
+    (strip k >= 1 stores from k*OW + HALO, the last strip from W - 64*V + HALO), and the first row of
+    each band (and the row before it) for the given band heights. Grid geometry only."""
+    halo = -(-TL // V) * V
+    ow = 64 * V - 2 * halo
+    cols = set()
+    if W % V == 0 and W >= 64 * V:
+        strips = -(-(W - 64 * V) // ow) + 1
+        starts = [k * ow + halo for k in range(1, strips - 1)] + [W - 64 * V + halo]
+    else:
+        starts = [k * ow for k in range(1, -(-(W - 1) // ow))]
+    for c0 in starts:
+        cols.update((c0 - 1, c0))
+    rows = set()
+    for band in bands:
+        for rb in range(1 + band, H - 1, band):
+            rows.update((rb - 1, rb))
+    return sorted(rows), sorted(cols)
+
+
+def sample_points(H: int, W: int, n: int, seed: int = 0, stream=None):
+    """Corners, ring points, tile-edge points and random interior points. With stream = (V, TL), also
+    points where band-edge rows meet strip-edge columns of the streaming kernel of that geometry."""
     rng = np.random.default_rng(seed)
     pts = {(0, 0), (H - 1, W - 1), (1, 1), (H - 2, W - 2), (1, W - 2), (H - 2, 1), (0, W // 2)}
     for r in (7, 8, 9, 15, 16, 17):
         for cc in (255, 256, 511, 512, 513):
             if 0 < r < H - 1 and 0 < cc < W - 1:
                 pts.add((r, cc))
+    if stream is not None:
+        rows, cols = stream_edges(H, W, *stream)
+        picks = rng.permutation(len(rows) * len(cols))[: max(8, n // 2)]
+        for k in picks:
+            r, cc = rows[k // len(cols)], cols[k % len(cols)]
+            if 0 < r < H - 1 and 0 < cc < W - 1:
+                pts.add((int(r), int(cc)))
     while len(pts) < n:
         pts.add((int(rng.integers(0, H)), int(rng.integers(0, W))))
     return sorted(pts)

@@ -33,6 +33,18 @@ def test_traffic_record_dropped_when_kernel_changes(tmp_path):
 
 def test_cpu_baseline_sample():
     r = bench.cpu_baseline(normal_grid(66, 130, seed=1), T_step=10, budget_s=0.2)
-    assert r["kind"] == "oracle" and r["unit"] == "GB/s"
-    assert r["cores"] >= 1 and r["value"] > 0
+    assert r["kind"] == "oracle" and r["unit"] == "GFLOP/s"
+    assert r["cores"] == bench.host_cores() and r["value"] > 0
+    # GFLOP/s at 4 operations and GB/s at 16 B per point and sweep describe the same sweeps
+    assert abs(r["effective_GBps_at_16B"] - 4.0 * r["value"]) <= 5 * 0.0005  # both rounded to 3 decimals
     assert "sweeps in" in r["sample"] and "calls of" in r["sample"]
+
+
+def test_host_cores_is_nproc():
+    import os
+    import subprocess
+
+    out = subprocess.run(["nproc"], capture_output=True, text=True)
+    if out.returncode == 0:
+        assert bench.host_cores() == int(out.stdout.strip())
+    assert 1 <= bench.host_cores() <= (os.cpu_count() or 1)
