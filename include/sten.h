@@ -478,6 +478,26 @@ sten_status sten_jacobi5_adjoint_f32_seg(const float* lam_in, const float* state
 /* *out = sum of partials[0..n) in a fixed order (one workgroup). */
 sten_status sten_reduce_f64(const double* partials, int64_t n, double* out, hipStream_t stream);
 
+/*
+ * For callers that cannot allocate device memory at call time (code under HIP
+ * graph capture, tight serving loops): sten_jacobi5_adjoint_f32_seg with the
+ * FP64 partial sums kept by the library, followed, when dLdc is not NULL, by
+ * sten_reduce_f64 of those sums into *dLdc (device memory, one double).
+ * Same bits as the two calls it replaces. The partial sums live in a static
+ * per-device buffer of 2^20 doubles (8 MiB), held until the process ends;
+ * grids needing more (sten_adjoint_partials_len(H, W) > 2^20) are rejected
+ * with STEN_ERR_WORKSPACE. The buffer keeps the last call's sums: reset != 0
+ * clears them (a fill kernel, no memset), reset == 0 adds this segment to
+ * them, so a checkpointed reverse pass calls it once per segment, the first
+ * with reset set, and *dLdc holds the running total after each call. All
+ * calls on one device share the buffer: calls that overlap on one device
+ * (other threads or streams) race. The lambda ping-pong grid `work` is the
+ * caller's, as for sten_jacobi5_adjoint_f32_seg. Allocates nothing.
+ */
+sten_status sten_jacobi5_adjoint_f32_seg_noalloc(const float* lam_in, const float* states, int32_t nsteps,
+                                                 float* lam_out, float* work, int32_t reset, double* dLdc,
+                                                 int64_t H, int64_t W, int64_t ld, float c, hipStream_t stream);
+
 /* ------------------------------------------------------------------------ */
 /* Tiled execution on one GPU (chares with ghost exchange)                   */
 /* ------------------------------------------------------------------------ */

@@ -92,6 +92,8 @@ SIGNATURES = {
     "sten_jacobi5_adjoint_f32_seg": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _vp, _i32, _i64, _i64, _i64,
                                                     _f32, _vp]),
     "sten_reduce_f64": (ctypes.c_int, [_vp, _i64, _vp, _vp]),
+    "sten_jacobi5_adjoint_f32_seg_noalloc": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _i32, _vp, _i64, _i64, _i64,
+                                                            _f32, _vp]),
     "sten_tiled_workspace_bytes": (_sz, [_i64, _i64, _i32, _i32]),
     "sten_tiled_create": (ctypes.c_int, [_i64, _i64, _i32, _i32, _vp, _sz, ctypes.POINTER(_vp)]),
     "sten_sweep_chain_f64": (ctypes.c_int, [_vp, _vp, _i64, _i64, _i64, _i32, _f64, _vp]),

@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "common.hpp"
 
@@ -164,6 +165,79 @@ sten_status check_dims(int64_t H, int64_t W, int64_t ld, int32_t T) {
     return STEN_OK;
 }
 
+// The transposed steps of one segment; `partials` (when not NULL) holds at
+// least adj_blocks(H, W) doubles of device memory, queried here when
+// check_partials is set (the library's own static buffer is not).
+sten_status adjoint_seg(const float* lam_in, const float* states, int32_t nsteps, float* lam_out, float* work,
+                        double* partials, bool check_partials, int32_t reset, int64_t H, int64_t W, int64_t ld,
+                        float c, hipStream_t stream) {
+    sten_status st = check_dims(H, W, ld, nsteps);
+    if (st != STEN_OK || H == 0 || W == 0) return st;
+    if (lam_in == nullptr || lam_out == nullptr) return STEN_ERR_PTR;
+    const bool need_work = nsteps >= 2;
+    if (need_work && work == nullptr) return STEN_ERR_PTR;
+    const size_t gb = span_bytes(H, W, ld, 4);
+    if (overlaps(lam_in, gb, lam_out, gb)) return STEN_ERR_ALIAS;
+    if (need_work && (overlaps(lam_in, gb, work, gb) || overlaps(lam_out, gb, work, gb))) return STEN_ERR_ALIAS;
+    const int64_t pstride = H * ld;
+    if (states != nullptr && nsteps > 0) {
+        const size_t sb = (size_t)(nsteps - 1) * pstride * 4 + gb;
+        if (overlaps(states, sb, lam_out, gb) || (need_work && overlaps(states, sb, work, gb)))
+            return STEN_ERR_ALIAS;
+    }
+    if (!is_device_ptr(lam_in) || !is_device_ptr(lam_out) || (need_work && !is_device_ptr(work)))
+        return STEN_ERR_PTR;
+    if (states != nullptr && !is_device_ptr(states)) return STEN_ERR_PTR;
+    if (check_partials && partials != nullptr && !is_device_ptr(partials)) return STEN_ERR_PTR;
+    const int h = (int)H, w = (int)W;
+    const uint32_t nb = adj_blocks(H, W);
+    const bool degenerate = (H < 3 || W < 3);
+    if (partials != nullptr && reset && (nsteps == 0 || degenerate || states == nullptr))
+        fill_f64_kernel<<<grid_for(nb), 256, 0, stream>>>(partials, nb, 0.0);
+    if (nsteps == 0 || degenerate) {
+        copy_f32_kernel<<<grid_for(H * W), 256, 0, stream>>>(lam_in, lam_out, h, w, ld);
+        return check_launch();
+    }
+    const float* src = lam_in;
+    for (int32_t s = 1; s <= nsteps; ++s) {
+        float* dst = ((nsteps - s) % 2 == 0) ? lam_out : work;
+        const float* u = states != nullptr ? states + (int64_t)(nsteps - s) * pstride : nullptr;
+        const int acc = (s == 1 && reset) ? 0 : 1;
+        adjoint_step_kernel<<<nb, kAdjBlock, 0, stream>>>(src, u, dst, u != nullptr ? partials : nullptr, acc, h, w,
+                                                         ld, c, adj_tiles_x(W));
+        src = dst;
+    }
+    return check_launch();
+}
+
+// FP64 partial sums of sten_jacobi5_adjoint_f32_seg_noalloc, one per
+// workgroup of a transposed step, in a per-device static buffer, so that the
+// call allocates nothing. Every call on a device shares that device's buffer.
+constexpr size_t kStaticPartials = (size_t)1 << 20;  // 8 MiB per device
+static __device__ __align__(256) double scratch[kStaticPartials];
+
+// Device address of `scratch` on each device, taken once per device with that
+// device current (in host code the array's name is not a device address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+sten_status scratch_partials(double** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e);
+    if (dev < 0 || dev >= kMaxDevices) return STEN_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e);
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return STEN_OK;
+}
+
 }  // namespace
 }  // namespace sten
 
@@ -204,44 +278,7 @@ sten_status sten_jacobi5_f32_states(const float* u0, float* states, int64_t H, i
 sten_status sten_jacobi5_adjoint_f32_seg(const float* lam_in, const float* states, int32_t nsteps, float* lam_out,
                                          float* work, double* partials, int32_t reset, int64_t H, int64_t W,
                                          int64_t ld, float c, hipStream_t stream) {
-    using namespace sten;
-    sten_status st = check_dims(H, W, ld, nsteps);
-    if (st != STEN_OK || H == 0 || W == 0) return st;
-    if (lam_in == nullptr || lam_out == nullptr) return STEN_ERR_PTR;
-    const bool need_work = nsteps >= 2;
-    if (need_work && work == nullptr) return STEN_ERR_PTR;
-    const size_t gb = span_bytes(H, W, ld, 4);
-    if (overlaps(lam_in, gb, lam_out, gb)) return STEN_ERR_ALIAS;
-    if (need_work && (overlaps(lam_in, gb, work, gb) || overlaps(lam_out, gb, work, gb))) return STEN_ERR_ALIAS;
-    const int64_t pstride = H * ld;
-    if (states != nullptr && nsteps > 0) {
-        const size_t sb = (size_t)(nsteps - 1) * pstride * 4 + gb;
-        if (overlaps(states, sb, lam_out, gb) || (need_work && overlaps(states, sb, work, gb)))
-            return STEN_ERR_ALIAS;
-    }
-    if (!is_device_ptr(lam_in) || !is_device_ptr(lam_out) || (need_work && !is_device_ptr(work)))
-        return STEN_ERR_PTR;
-    if (states != nullptr && !is_device_ptr(states)) return STEN_ERR_PTR;
-    if (partials != nullptr && !is_device_ptr(partials)) return STEN_ERR_PTR;
-    const int h = (int)H, w = (int)W;
-    const uint32_t nb = adj_blocks(H, W);
-    const bool degenerate = (H < 3 || W < 3);
-    if (partials != nullptr && reset && (nsteps == 0 || degenerate || states == nullptr))
-        fill_f64_kernel<<<grid_for(nb), 256, 0, stream>>>(partials, nb, 0.0);
-    if (nsteps == 0 || degenerate) {
-        copy_f32_kernel<<<grid_for(H * W), 256, 0, stream>>>(lam_in, lam_out, h, w, ld);
-        return check_launch();
-    }
-    const float* src = lam_in;
-    for (int32_t s = 1; s <= nsteps; ++s) {
-        float* dst = ((nsteps - s) % 2 == 0) ? lam_out : work;
-        const float* u = states != nullptr ? states + (int64_t)(nsteps - s) * pstride : nullptr;
-        const int acc = (s == 1 && reset) ? 0 : 1;
-        adjoint_step_kernel<<<nb, kAdjBlock, 0, stream>>>(src, u, dst, u != nullptr ? partials : nullptr, acc, h, w,
-                                                         ld, c, adj_tiles_x(W));
-        src = dst;
-    }
-    return check_launch();
+    return sten::adjoint_seg(lam_in, states, nsteps, lam_out, work, partials, true, reset, H, W, ld, c, stream);
 }
 
 sten_status sten_jacobi5_adjoint_f32(const float* gout, float* gin, float* work, int64_t H, int64_t W, int64_t ld,
@@ -255,6 +292,28 @@ sten_status sten_reduce_f64(const double* partials, int64_t n, double* out, hipS
     if (partials == nullptr || out == nullptr) return STEN_ERR_PTR;
     if (!is_device_ptr(partials) || !is_device_ptr(out)) return STEN_ERR_PTR;
     reduce_f64_kernel<<<1, kAdjBlock, 0, stream>>>(partials, n, out);
+    return check_launch();
+}
+
+sten_status sten_jacobi5_adjoint_f32_seg_noalloc(const float* lam_in, const float* states, int32_t nsteps,
+                                                 float* lam_out, float* work, int32_t reset, double* dLdc,
+                                                 int64_t H, int64_t W, int64_t ld, float c, hipStream_t stream) {
+    using namespace sten;
+    sten_status st = check_dims(H, W, ld, nsteps);
+    if (st != STEN_OK) return st;
+    if (H == 0 || W == 0) return STEN_OK;
+    if (sten_adjoint_partials_len(H, W) > kStaticPartials) return STEN_ERR_WORKSPACE;
+    if (dLdc != nullptr) {
+        const size_t gb = span_bytes(H, W, ld, 4);
+        if (overlaps(dLdc, sizeof(double), lam_out, gb) || (nsteps >= 2 && overlaps(dLdc, sizeof(double), work, gb)))
+            return STEN_ERR_ALIAS;
+        if (!is_device_ptr(dLdc)) return STEN_ERR_PTR;
+    }
+    double* partials = nullptr;
+    if ((st = scratch_partials(&partials)) != STEN_OK) return st;
+    st = adjoint_seg(lam_in, states, nsteps, lam_out, work, partials, false, reset, H, W, ld, c, stream);
+    if (st != STEN_OK || dLdc == nullptr) return st;
+    reduce_f64_kernel<<<1, kAdjBlock, 0, stream>>>(partials, (int64_t)sten_adjoint_partials_len(H, W), dLdc);
     return check_launch();
 }
 
