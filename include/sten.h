@@ -522,7 +522,8 @@ typedef struct sten_tiled_s* sten_tiled_handle;
 typedef enum { STEN_TILED_PACKED = 0, STEN_TILED_DIRECT = 1 } sten_tiled_mode;
 
 /* Device workspace bytes for a tiling with ghost depth 1, packed mode (0 when
- * the tiling is invalid: H, W, pr, pc < 1 or more tiles than rows/columns). */
+ * the tiling is invalid: H, W, pr, pc < 1, more tiles than rows/columns, or
+ * more than 65536 tiles in all). */
 size_t sten_tiled_workspace_bytes(int64_t H, int64_t W, int32_t pr, int32_t pc);
 
 /* Device workspace bytes for a tiling with ghost depth `ghost` (1..12) and

@@ -262,3 +262,19 @@ def test_workspace_query_errors(lib):
     assert q(_lib.OP_BATCH, 2**31, 0, 0) == bad
     # 2^30 x 2^30 FP32 states x (2^31) grids overflow size_t
     assert q(_lib.OP_STATES, 1 << 30, 1 << 30, 2**31 - 1) == bad
+
+
+def test_tiled_tile_count_capped(lib):
+    """A tiling of more than 65536 tiles is refused (the planner's host tables grow with the tile count)."""
+    assert lib.sten_tiled_workspace_bytes(4096, 4096, 256, 256) > 0      # 65536 tiles
+    assert lib.sten_tiled_workspace_bytes(4096, 4096, 257, 256) == 0     # one row of tiles more
+    assert lib.sten_tiled_workspace_bytes(2**30, 2**30, 2, 2**30) == 0
+
+
+def test_tiled_plan_check_large_ghost_strips(lib):
+    """Ghost blocks of more than 2^31 elements (12 x a 2^28-column tile) are planned without overflow."""
+    import ctypes
+
+    info = (ctypes.c_int64 * 4)()
+    st = lib.sten_tiled_plan_check(2 * 2**28, 2**28, 2, 1, 1, 1, info, 4)
+    assert st in (0, -6)  # planned (or refused by a layout check), never a crash or garbage
