@@ -72,4 +72,9 @@ constexpr int kMaxStreamGridsPerLaunch = 32;
 // Returns false, with nothing launched, for levels outside 1..12.
 bool launch_stream_grids_f64(const GridView<double>* views, int n, double c, int levels, hipStream_t s);
 
+// One sweep of each of n FP64 grids (sweep.hip), in launches of up to 32
+// grids. Every grid: H, W >= 3, 16-byte aligned, even ld; returns false, with
+// nothing launched, otherwise.
+bool launch_sweep_grids_f64(const GridView<double>* views, int n, double c, hipStream_t s);
+
 }  // namespace sten

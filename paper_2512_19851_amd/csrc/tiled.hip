@@ -43,6 +43,9 @@ namespace sten {
 void launch_sweep_f64_internal(const double* in, double* out, int H, int W, int64_t ld, double c, hipStream_t s);
 
 constexpr int kMaxGhost = 12;
+// Most tiles per tiling: the plan keeps host tables per tile and per message,
+// so an unbounded count would let a caller's sizes exhaust host memory.
+constexpr int64_t kMaxTiles = (int64_t)1 << 16;
 
 namespace {
 
@@ -110,7 +113,8 @@ struct sten_tiled_s {
     std::vector<sten::Strip> h_pack[2], h_unpack[2];
     sten::Strip* d_pack[2] = {nullptr, nullptr};
     sten::Strip* d_unpack[2] = {nullptr, nullptr};
-    int n_strips = 0, max_strip = 0;  // messages per exchange, largest (elements)
+    int n_strips = 0;                 // messages per exchange
+    int64_t max_strip = 0;            // largest message (elements; g x a tile side can pass 2^31)
     int cur = 0;                      // buffer holding the current state
     int64_t local_epoch[2] = {0, 0};
     int64_t ghost_epoch[2] = {0, 0};
@@ -144,6 +148,7 @@ struct Layout {
 std::vector<Tile> make_tiles(int64_t H, int64_t W, int pr, int pc, int g) {
     std::vector<Tile> tiles;
     if (H < 1 || W < 1 || pr < 1 || pc < 1 || pr > H || pc > W || g < 1 || g > kMaxGhost) return tiles;
+    if ((int64_t)pr * pc > kMaxTiles) return tiles;
     if (H > INT32_MAX / 2 || W > INT32_MAX / 2) return tiles;
     for (int a = 0; a < pr; ++a) {
         for (int b = 0; b < pc; ++b) {
@@ -274,7 +279,7 @@ void build_plan(sten_tiled_s* p, const Layout& L, char* base) {
                 } else {
                     p->h_pack[k].push_back(Strip{at(N, k, src), at(T, k, dst), N.ldt, T.ldt, dst.rows, dst.cols});
                 }
-                p->max_strip = std::max(p->max_strip, dst.rows * dst.cols);
+                p->max_strip = std::max(p->max_strip, (int64_t)dst.rows * dst.cols);
             }
         }
     }
@@ -362,7 +367,7 @@ sten_status exchange(sten_tiled_s* p, int k, hipStream_t compute, hipStream_t co
             if (e == hipSuccess) e = hipStreamWaitEvent(comm, p->ev_compute, 0);
             if (e != hipSuccess) return hip_fail(e);
         }
-        const uint32_t gx = (uint32_t)std::min(64, std::max(1, (p->max_strip + 255) / 256));
+        const uint32_t gx = (uint32_t)std::min<int64_t>(64, std::max<int64_t>(1, (p->max_strip + 255) / 256));
         const int n = p->n_strips;
         strip_copy_kernel<<<dim3(gx, n), 256, 0, comm>>>(p->d_pack[k], n);
         if (p->mode == 0) strip_copy_kernel<<<dim3(gx, n), 256, 0, comm>>>(p->d_unpack[k], n);
@@ -377,18 +382,11 @@ sten_status exchange(sten_tiled_s* p, int k, hipStream_t compute, hipStream_t co
     return check_launch();
 }
 
-// s sweeps of every tile from buffer src to buffer 1 - src.
+// s sweeps of every tile from buffer src to buffer 1 - src: one sweep as one
+// launch of the single-sweep kernel over all tiles (per 32 tiles), several as
+// one launch of the streaming blocked kernel over all tiles (per 32 tiles).
 void sweep_tiles(sten_tiled_s* p, int src, int s, double c, hipStream_t compute) {
     const int dst = 1 - src;
-    if (s == 1) {
-        for (const Tile& t : p->tiles) {
-            const View v = tile_view(t, p->g);
-            if (v.vh < 3 || v.vw < 3) continue;
-            launch_sweep_f64_internal(t.buf[src] + v.off, t.buf[dst] + v.off, v.vh, v.vw, t.ldt, c, compute);
-            ++p->n_sweep_launches;
-        }
-        return;
-    }
     std::vector<GridView<double>> views;
     for (const Tile& t : p->tiles) {
         const View v = tile_view(t, p->g);
@@ -396,8 +394,21 @@ void sweep_tiles(sten_tiled_s* p, int src, int s, double c, hipStream_t compute)
         views.push_back(GridView<double>{t.buf[src] + v.off, t.buf[dst] + v.off, v.vh, v.vw, t.ldt});
     }
     if (views.empty()) return;
+    const int64_t launches = ((int64_t)views.size() + kMaxStreamGridsPerLaunch - 1) / kMaxStreamGridsPerLaunch;
+    if (s == 1) {
+        if (launch_sweep_grids_f64(views.data(), (int)views.size(), c, compute)) {
+            p->n_sweep_launches += launches;
+            return;
+        }
+        // a view off the 16-byte alignment the plan lays out: one launch per tile
+        for (const GridView<double>& v : views) {
+            launch_sweep_f64_internal(v.in, v.out, v.H, v.W, v.ld, c, compute);
+            ++p->n_sweep_launches;
+        }
+        return;
+    }
     launch_stream_grids_f64(views.data(), (int)views.size(), c, s, compute);
-    p->n_sweep_launches += ((int64_t)views.size() + kMaxStreamGridsPerLaunch - 1) / kMaxStreamGridsPerLaunch;
+    p->n_sweep_launches += launches;
 }
 
 sten_status make_plan(int64_t H, int64_t W, int pr, int pc, int g, int mode, sten_tiled_s* p, Layout& L) {

@@ -195,3 +195,18 @@ def test_invalid_ghost_depth(ops):
 def test_invalid_tiling(ops):
     with pytest.raises(ValueError):
         ops.TiledGrid(4, 4, 5, 1)
+
+
+@pytest.mark.parametrize("exchange", ["packed", "direct"])
+def test_tiled_depth1_one_launch_per_sweep(ops, exchange):
+    """Depth-1 ghosts: each sweep is one launch of the single-sweep kernel over all tiles (per 32 tiles),
+    bit-identical to the single grid; 42 tiles take two launches per sweep, 4 x 4 tiles one."""
+    for (pr, pc, launches) in [(6, 7, 2), (4, 4, 1)]:
+        u0 = normal_grid(200, 301, seed=pr * pc)
+        say(f"tiled depth 1 {exchange} {pr}x{pc}")
+        t = ops.TiledGrid(200, 301, pr, pc, ghost=1, exchange=exchange)
+        t.scatter(to_dev(u0))
+        t.run(5)
+        assert np.array_equal(to_host(t.gather()), oracle.jacobi5(u0, 5))
+        st = t.stats()
+        assert st["sweep_launches"] == 5 * launches
