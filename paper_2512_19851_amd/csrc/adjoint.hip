@@ -23,6 +23,7 @@
 #include <mutex>
 
 #include "common.hpp"
+#include "stream_common.hpp"
 
 namespace sten {
 
@@ -32,15 +33,16 @@ void launch_sweep_f32_internal(const float* in, float* out, int H, int W, int64_
 namespace {
 
 constexpr int kAdjBlock = 256;
-constexpr int kAdjRows = 8;
+constexpr int kAdjRows = 2;       // rows per tile of the fused one-step kernel
+constexpr int kAdjTbRows = 4;     // output rows per tile of the several-step kernel
+constexpr int kAdjMaxLevels = 4;  // transposed steps per launch of the several-step kernel
 
-__device__ __forceinline__ float interior_val(const float* __restrict__ g, int i, int j, int H, int W, int64_t ld) {
-    return (i >= 1 && i <= H - 2 && j >= 1 && j <= W - 2) ? g[(int64_t)i * ld + j] : 0.0f;
-}
+constexpr int kAdjTileBlock = kWave;  // one wave (256 columns) per workgroup of the fused one-step kernel
 
-// Sum of a double over the workgroup (fixed order: lanes by shuffle tree, then waves in order).
+// Sum of a double over a workgroup of NT lanes (fixed order: lanes by shuffle tree, then waves in order).
+template <int NT>
 __device__ double block_sum(double v) {
-    __shared__ double wsum[kAdjBlock / kWave];
+    __shared__ double wsum[NT / kWave];
     for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_down(v, off);
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
@@ -48,56 +50,245 @@ __device__ double block_sum(double v) {
     __syncthreads();
     double t = 0.0;
     if (threadIdx.x == 0)
-        for (int w = 0; w < (int)(blockDim.x / kWave); ++w) t += wsum[w];
+        for (int w = 0; w < NT / kWave; ++w) t += wsum[w];
     __syncthreads();
     return t;
 }
 
-// One transposed step: out = S^T g; when u is given, partials[block] (+)=
-// sum over this tile's interior points m of g[m] * nbrsum(u)[m].
-__global__ __launch_bounds__(kAdjBlock) void adjoint_step_kernel(const float* __restrict__ g,
+// Both kernels below evaluate one transposed step per point exactly as the
+// definition above: the four neighbour terms in the order N, S, W, E, each an
+// exact zero unless that neighbour is an interior point, summed left to right
+// in FP32, one multiplication by c, and on the ring one addition of the
+// point's own value first (g + c * sum). Every grid point is written.
+//
+// Column facts of one element: column j of a W-column grid.
+struct AdjCol {
+    bool in;    // j is an interior column
+    bool west;  // j - 1 is an interior column
+    bool east;  // j + 1 is an interior column
+};
+__device__ __forceinline__ AdjCol adj_col(int j, int W) {
+    return AdjCol{j >= 1 && j <= W - 2, j >= 2 && j <= W - 1, j >= 0 && j <= W - 3};
+}
+__device__ __forceinline__ bool adj_interior_row(int r, int H) { return r >= 1 && r <= H - 2; }
+
+// One transposed point: n, s, w, e are the four neighbours' values, m the
+// point's own; rn, rs: rows above and below are interior; rin: own row interior.
+__device__ __forceinline__ float adj_point(float n, float s, float w, float e, float m, bool rn, bool rs, bool rin,
+                                           const AdjCol& col, float c) {
+    float t = (rn && col.in ? n : 0.0f) + (rs && col.in ? s : 0.0f);
+    t = t + (rin && col.west ? w : 0.0f);
+    t = t + (rin && col.east ? e : 0.0f);
+    const float v = c * t;
+    return (rin && col.in) ? v : m + v;
+}
+
+constexpr int kAdjV = 4;  // floats per lane: one 16-byte vector
+
+// Row r of g (zeros outside the grid) into x: columns j0 .. j0+3.
+template <bool VEC>
+__device__ __forceinline__ void adj_load(const float* __restrict__ g, int r, int H, int W, int64_t ld, int j0,
+                                         float (&x)[kAdjV]) {
+    if (r < 0 || r >= H) {
+#pragma unroll
+        for (int e = 0; e < kAdjV; ++e) x[e] = 0.0f;
+        return;
+    }
+    const float* row = g + (int64_t)r * ld;
+    if (VEC && j0 >= 0 && j0 + kAdjV <= W) {
+        typedef float F4 __attribute__((ext_vector_type(4)));
+        const F4 v = *reinterpret_cast<const F4*>(row + j0);
+#pragma unroll
+        for (int e = 0; e < kAdjV; ++e) x[e] = v[e];
+    } else {
+#pragma unroll
+        for (int e = 0; e < kAdjV; ++e) x[e] = (j0 + e >= 0 && j0 + e < W) ? row[j0 + e] : 0.0f;
+    }
+}
+
+// Columns j0 .. j0+3 of row r (inside the grid) where they lie in [lo, hi).
+template <bool VEC>
+__device__ __forceinline__ void adj_store(float* __restrict__ out, int r, int64_t ld, int j0, int lo, int hi,
+                                          const float (&x)[kAdjV]) {
+    float* row = out + (int64_t)r * ld;
+    if (VEC && j0 >= lo && j0 + kAdjV <= hi) {
+        typedef float F4 __attribute__((ext_vector_type(4)));
+        F4 v;
+#pragma unroll
+        for (int e = 0; e < kAdjV; ++e) v[e] = x[e];
+        *reinterpret_cast<F4*>(row + j0) = v;
+    } else {
+#pragma unroll
+        for (int e = 0; e < kAdjV; ++e)
+            if (j0 + e >= lo && j0 + e < hi) row[j0 + e] = x[e];
+    }
+}
+
+// One transposed step, fused with the dL/dc term when u is given:
+// partials[block] (+)= sum over this tile's interior points m of
+// g[m] * nbrsum(u)[m] (FP32 neighbour sum in the order N, S, W, E, product
+// and sum in FP64). A workgroup of one wave owns a tile of ROWS rows by 256
+// columns (4 floats per lane; small tiles, so that even a 1024^2 grid has
+// thousands of waves); a lane keeps its column vector of the tile's ROWS + 2
+// rows of g (and u) in registers and walks down; the neighbours across lanes come from DPP lane
+// shifts, and the wave's two edge lanes load the one column that lies in the
+// next tile. Each workgroup owns a fixed tile, so the partial sums, and their
+// reduction, are deterministic.
+template <int ROWS, bool VEC, bool DOT>
+__global__ __launch_bounds__(kAdjTileBlock) void adjoint_tile_kernel(const float* __restrict__ g,
                                                                  const float* __restrict__ u,
                                                                  float* __restrict__ out,
                                                                  double* __restrict__ partials, int accumulate,
                                                                  int H, int W, int64_t ld, float c,
                                                                  uint32_t tiles_x) {
+    using stream::lane_from_lower;
+    using stream::lane_from_upper;
     const uint32_t tile = xcd_tile_of_block(blockIdx.x, gridDim.x);
     const uint32_t ty = tile / tiles_x;
     const uint32_t tx = tile - ty * tiles_x;
-    const int j = (int)tx * kAdjBlock + (int)threadIdx.x;
-    const int i0 = (int)ty * kAdjRows;
-    double acc = 0.0;
-    if (j < W) {
-        const bool ring_col = (j == 0 || j == W - 1);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int j0 = ((int)tx * kAdjTileBlock + (int)threadIdx.x) * kAdjV;
+    const int i0 = (int)ty * ROWS;  // first output row (every grid row is an output row)
+    float a[ROWS + 2][kAdjV];
+    float q[DOT ? ROWS + 2 : 1][kAdjV];
 #pragma unroll
-        for (int r = 0; r < kAdjRows; ++r) {
-            const int i = i0 + r;
-            if (i < H) {
-                const float tn = interior_val(g, i - 1, j, H, W, ld);
-                const float ts = interior_val(g, i + 1, j, H, W, ld);
-                const float tw = interior_val(g, i, j - 1, H, W, ld);
-                const float te = interior_val(g, i, j + 1, H, W, ld);
-                float s = tn + ts;
-                s = s + tw;
-                s = s + te;
-                const float gc = g[(int64_t)i * ld + j];
-                const bool ring = ring_col || i == 0 || i == H - 1;
-                const float cs = c * s;
-                out[(int64_t)i * ld + j] = ring ? gc + cs : cs;
-                if (u != nullptr && !ring) {
-                    const int64_t q = (int64_t)i * ld + j;
-                    float ns = u[q - ld] + u[q + ld];
-                    ns = ns + u[q - 1];
-                    ns = ns + u[q + 1];
-                    acc += (double)gc * (double)ns;
+    for (int k = 0; k < ROWS + 2; ++k) {
+        adj_load<VEC>(g, i0 - 1 + k, H, W, ld, j0, a[k]);
+        if constexpr (DOT) adj_load<VEC>(u, i0 - 1 + k, H, W, ld, j0, q[k]);
+    }
+    AdjCol col[kAdjV];
+#pragma unroll
+    for (int e = 0; e < kAdjV; ++e) col[e] = adj_col(j0 + e, W);
+    const bool edge_w = lane == 0 && j0 > 0 && j0 <= W;                  // column j0 - 1 lies in another wave
+    const bool edge_e = lane == kWave - 1 && j0 + kAdjV < W;             // column j0 + 4 lies in another wave
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < ROWS; ++k) {
+        const int r = i0 + k;
+        if (r < H) {  // uniform over the workgroup
+            const float* grow = g + (int64_t)r * ld;
+            float lft = lane_from_lower(a[k + 1][kAdjV - 1]);
+            float rgt = lane_from_upper(a[k + 1][0]);
+            if (edge_w) lft = grow[j0 - 1];
+            if (edge_e) rgt = grow[j0 + kAdjV];
+            const bool rn = adj_interior_row(r - 1, H), rs = adj_interior_row(r + 1, H), rin = adj_interior_row(r, H);
+            float o[kAdjV];
+#pragma unroll
+            for (int e = 0; e < kAdjV; ++e) {
+                const float w = e == 0 ? lft : a[k + 1][e > 0 ? e - 1 : 0];
+                const float ea = e == kAdjV - 1 ? rgt : a[k + 1][e < kAdjV - 1 ? e + 1 : 0];
+                o[e] = adj_point(a[k][e], a[k + 2][e], w, ea, a[k + 1][e], rn, rs, rin, col[e], c);
+            }
+            adj_store<VEC>(out, r, ld, j0, 0, W, o);
+            if constexpr (DOT) {
+                if (rin) {
+                    const float* urow = u + (int64_t)r * ld;
+                    float ul = lane_from_lower(q[k + 1][kAdjV - 1]);
+                    float ur = lane_from_upper(q[k + 1][0]);
+                    if (edge_w) ul = urow[j0 - 1];
+                    if (edge_e) ur = urow[j0 + kAdjV];
+#pragma unroll
+                    for (int e = 0; e < kAdjV; ++e) {
+                        if (col[e].in) {
+                            const float uw = e == 0 ? ul : q[k + 1][e > 0 ? e - 1 : 0];
+                            const float ue = e == kAdjV - 1 ? ur : q[k + 1][e < kAdjV - 1 ? e + 1 : 0];
+                            float ns = q[k][e] + q[k + 2][e];
+                            ns = ns + uw;
+                            ns = ns + ue;
+                            acc += (double)a[k + 1][e] * (double)ns;
+                        }
+                    }
                 }
             }
         }
     }
-    if (partials != nullptr) {
-        const double t = block_sum(acc);
+    if constexpr (DOT) {
+        const double t = block_sum<kAdjTileBlock>(acc);
         if (threadIdx.x == 0) partials[blockIdx.x] = accumulate ? partials[blockIdx.x] + t : t;
     }
+}
+
+// TL transposed steps per launch (no dL/dc), the register-tile form of
+// temporal blocking: a wave loads a tile of ROWS + 2*TL rows by 256 columns
+// (4 floats per lane; zeros outside the grid) and applies TL steps in
+// registers. After step s the values are exact on the tile shrunk by s on
+// every side (a point needs only its four neighbours of the step before), so
+// the central ROWS rows by 256 - 2*HALO columns (HALO = TL rounded up to a
+// multiple of 4) are exact after TL steps and stored. Points outside the grid
+// are never interior, so they never feed a value; they are never stored.
+// INNER: every loaded point is an interior point, so no term is masked and no
+// point is on the ring: the step is the plain five-point expression.
+template <int ROWS, int TL, bool VEC, bool INNER>
+__device__ __forceinline__ void adjoint_tb_tile(const float* __restrict__ g, float* __restrict__ out, int H, int W,
+                                                int64_t ld, float c, int cs, int r0) {
+    using stream::lane_from_lower;
+    using stream::lane_from_upper;
+    constexpr int NR = ROWS + 2 * TL;
+    constexpr int HALO = (TL + kAdjV - 1) / kAdjV * kAdjV;
+    constexpr int OW = kWave * kAdjV - 2 * HALO;
+    const int j0 = cs + (int)threadIdx.x * kAdjV;
+    float a[NR][kAdjV];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) adj_load<VEC>(g, r0 + k, H, W, ld, j0, a[k]);
+    AdjCol col[kAdjV];
+#pragma unroll
+    for (int e = 0; e < kAdjV; ++e) col[e] = adj_col(j0 + e, W);
+#pragma unroll
+    for (int s = 1; s <= TL; ++s) {
+        // rows s-1 .. NR-s are exact; update rows s .. NR-1-s in place, top to bottom
+        float prev[kAdjV];
+#pragma unroll
+        for (int e = 0; e < kAdjV; ++e) prev[e] = a[s - 1][e];
+#pragma unroll
+        for (int k = s; k <= NR - 1 - s; ++k) {
+            const int r = r0 + k;
+            const float lft = lane_from_lower(a[k][kAdjV - 1]);
+            const float rgt = lane_from_upper(a[k][0]);
+            float nv[kAdjV];
+#pragma unroll
+            for (int e = 0; e < kAdjV; ++e) {
+                const float w = e == 0 ? lft : a[k][e > 0 ? e - 1 : 0];
+                const float ea = e == kAdjV - 1 ? rgt : a[k][e < kAdjV - 1 ? e + 1 : 0];
+                if constexpr (INNER) {
+                    float t = prev[e] + a[k + 1][e];
+                    t = t + w;
+                    t = t + ea;
+                    nv[e] = c * t;
+                } else {
+                    nv[e] = adj_point(prev[e], a[k + 1][e], w, ea, a[k][e], adj_interior_row(r - 1, H),
+                                      adj_interior_row(r + 1, H), adj_interior_row(r, H), col[e], c);
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < kAdjV; ++e) {
+                prev[e] = a[k][e];
+                a[k][e] = nv[e];
+            }
+        }
+    }
+    const int lo = max(cs + HALO, 0), hi = min(cs + HALO + OW, W);
+#pragma unroll
+    for (int k = TL; k < TL + ROWS; ++k) {
+        const int r = r0 + k;
+        if (r >= 0 && r < H) adj_store<VEC>(out, r, ld, j0, lo, hi, a[k]);
+    }
+}
+
+template <int ROWS, int TL, bool VEC>
+__global__ __launch_bounds__(kWave) void adjoint_tb_kernel(const float* __restrict__ g, float* __restrict__ out,
+                                                           int H, int W, int64_t ld, float c, uint32_t strips) {
+    constexpr int HALO = (TL + kAdjV - 1) / kAdjV * kAdjV;
+    constexpr int OW = kWave * kAdjV - 2 * HALO;
+    const uint32_t tile = xcd_tile_of_block(blockIdx.x, gridDim.x);
+    const uint32_t band = tile / strips;
+    const uint32_t strip = tile - band * strips;
+    const int cs = (int)strip * OW - HALO;  // first loaded column
+    const int r0 = (int)band * ROWS - TL;   // first loaded row
+    const bool inner = r0 >= 1 && r0 + ROWS + 2 * TL <= H - 1 && cs >= 1 && cs + kWave * kAdjV <= W - 1;
+    if (inner)
+        adjoint_tb_tile<ROWS, TL, VEC, true>(g, out, H, W, ld, c, cs, r0);
+    else
+        adjoint_tb_tile<ROWS, TL, VEC, false>(g, out, H, W, ld, c, cs, r0);
 }
 
 __global__ void fill_f64_kernel(double* p, int64_t n, double v) {
@@ -111,7 +302,7 @@ __global__ __launch_bounds__(kAdjBlock) void reduce_f64_kernel(const double* __r
                                                                double* __restrict__ out) {
     double v = 0.0;
     for (int64_t k = threadIdx.x; k < n; k += blockDim.x) v += p[k];
-    const double t = block_sum(v);
+    const double t = block_sum<kAdjBlock>(v);
     if (threadIdx.x == 0) *out = t;
 }
 
@@ -155,8 +346,40 @@ inline uint32_t grid_for(int64_t total) {
     return (uint32_t)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 65536));
 }
 
-inline uint32_t adj_tiles_x(int64_t W) { return ceil_div(W, kAdjBlock); }
+inline uint32_t adj_tiles_x(int64_t W) { return ceil_div(W, (int64_t)kAdjTileBlock * kAdjV); }
 inline uint32_t adj_blocks(int64_t H, int64_t W) { return adj_tiles_x(W) * ceil_div(H, kAdjRows); }
+
+template <bool VEC>
+void launch_adjoint_step(const float* g, const float* u, float* out, double* partials, int accumulate, int H, int W,
+                         int64_t ld, float c, hipStream_t s) {
+    const uint32_t nb = adj_blocks(H, W);
+    if (u != nullptr && partials != nullptr)
+        adjoint_tile_kernel<kAdjRows, VEC, true><<<nb, kAdjTileBlock, 0, s>>>(g, u, out, partials, accumulate, H,
+                                                                             W, ld, c, adj_tiles_x(W));
+    else
+        adjoint_tile_kernel<kAdjRows, VEC, false><<<nb, kAdjTileBlock, 0, s>>>(g, nullptr, out, nullptr, 0, H, W, ld,
+                                                                              c, adj_tiles_x(W));
+}
+
+template <int TL, bool VEC>
+void launch_adjoint_tb_levels(const float* g, float* out, int H, int W, int64_t ld, float c, hipStream_t s) {
+    constexpr int HALO = (TL + kAdjV - 1) / kAdjV * kAdjV;
+    constexpr int OW = kWave * kAdjV - 2 * HALO;
+    const uint32_t strips = ceil_div(W, OW);
+    const uint32_t bands = ceil_div(H, kAdjTbRows);
+    adjoint_tb_kernel<kAdjTbRows, TL, VEC><<<strips * bands, kWave, 0, s>>>(g, out, H, W, ld, c, strips);
+}
+
+// One launch of `levels` transposed steps (1..kAdjMaxLevels) from g into out.
+template <bool VEC>
+void launch_adjoint_tb(const float* g, float* out, int H, int W, int64_t ld, float c, int levels, hipStream_t s) {
+    switch (levels) {
+        case 1: launch_adjoint_tb_levels<1, VEC>(g, out, H, W, ld, c, s); break;
+        case 2: launch_adjoint_tb_levels<2, VEC>(g, out, H, W, ld, c, s); break;
+        case 3: launch_adjoint_tb_levels<3, VEC>(g, out, H, W, ld, c, s); break;
+        default: launch_adjoint_tb_levels<4, VEC>(g, out, H, W, ld, c, s); break;  // levels == 4
+    }
+}
 
 sten_status check_dims(int64_t H, int64_t W, int64_t ld, int32_t T) {
     if (H < 0 || W < 0 || T < 0) return STEN_ERR_ARG;
@@ -198,13 +421,34 @@ sten_status adjoint_seg(const float* lam_in, const float* states, int32_t nsteps
         copy_f32_kernel<<<grid_for(H * W), 256, 0, stream>>>(lam_in, lam_out, h, w, ld);
         return check_launch();
     }
+    const bool vec = ((((uintptr_t)lam_in | (uintptr_t)lam_out | (need_work ? (uintptr_t)work : 0) |
+                        (states != nullptr ? (uintptr_t)states : 0)) % 16) == 0) && ld % kAdjV == 0;
     const float* src = lam_in;
-    for (int32_t s = 1; s <= nsteps; ++s) {
-        float* dst = ((nsteps - s) % 2 == 0) ? lam_out : work;
-        const float* u = states != nullptr ? states + (int64_t)(nsteps - s) * pstride : nullptr;
-        const int acc = (s == 1 && reset) ? 0 : 1;
-        adjoint_step_kernel<<<nb, kAdjBlock, 0, stream>>>(src, u, dst, u != nullptr ? partials : nullptr, acc, h, w,
-                                                         ld, c, adj_tiles_x(W));
+    if (states != nullptr && partials != nullptr) {
+        // one fused launch per step: lambda_k from lambda_{k+1}, plus the step's dL/dc term
+        for (int32_t s = 1; s <= nsteps; ++s) {
+            float* dst = ((nsteps - s) % 2 == 0) ? lam_out : work;
+            const float* u = states + (int64_t)(nsteps - s) * pstride;
+            const int acc = (s == 1 && reset) ? 0 : 1;
+            if (vec)
+                launch_adjoint_step<true>(src, u, dst, partials, acc, h, w, ld, c, stream);
+            else
+                launch_adjoint_step<false>(src, u, dst, partials, acc, h, w, ld, c, stream);
+            src = dst;
+        }
+        return check_launch();
+    }
+    // no dL/dc: several steps per launch, the steps split as evenly as the launch count allows; the
+    // last launch writes lam_out
+    const int launches = (nsteps + kAdjMaxLevels - 1) / kAdjMaxLevels;
+    const int base = nsteps / launches, extra = nsteps % launches;
+    for (int k = 1; k <= launches; ++k) {
+        const int lev = base + (k <= extra ? 1 : 0);
+        float* dst = ((launches - k) % 2 == 0) ? lam_out : work;
+        if (vec)
+            launch_adjoint_tb<true>(src, dst, h, w, ld, c, lev, stream);
+        else
+            launch_adjoint_tb<false>(src, dst, h, w, ld, c, lev, stream);
         src = dst;
     }
     return check_launch();

@@ -167,3 +167,52 @@ def test_grad_without_c(ag):
     (gx,) = torch.autograd.grad((y.double() * to_dev(w32)).sum(), (x,))
     got = to_host(gx).astype(np.float64)
     assert np.all(np.abs(got - oracle.jacobi5_adjoint(w32, 4)) <= oracle.bound_adjoint_fp32(w32, 4))
+
+
+ADJ_SHAPES = [(3, 3), (4, 5), (17, 253), (40, 260), (33, 1030), (130, 301), (9, 1024), (261, 250)]
+
+
+@pytest.mark.parametrize("shape", ADJ_SHAPES, ids=lambda s: f"{s[0]}x{s[1]}")
+def test_adjoint_exact_many_steps(ag, shape):
+    """Small integers: every FP32 operation of up to 8 transposed steps is exact, so the result equals the
+    FP64 oracle bit for bit. Shapes cross the tiles (8 or 16 rows, 240-256 columns) and strips of both
+    kernels, with ragged last tiles and widths that are not a multiple of 4 (element-wise path); T = 7 and
+    8 take two launches of the several-step kernel."""
+    rng = np.random.default_rng(sum(shape))
+    w = rng.integers(-8, 9, shape).astype(np.float64)
+    g = to_dev(w.astype(np.float32))
+    for T in (1, 2, 3, 4, 5, 6, 7, 8):
+        say(f"adjoint exact {shape} T={T}")
+        got = to_host(ag.adjoint(g, T)).astype(np.float64)
+        want = oracle.jacobi5_adjoint(w, T)
+        assert np.array_equal(got, want), f"{shape} T={T}: max diff {np.max(np.abs(got - want))}"
+
+
+def test_adjoint_strided_views(ag):
+    """Row stride ld > W, not a multiple of 4 (the element-wise loads and stores), through the C ABI."""
+    import torch
+
+    from paper_2512_19851_amd import _lib
+
+    H, W, ld = 50, 203, 211
+    rng = np.random.default_rng(11)
+    w = rng.integers(-8, 9, (H, W)).astype(np.float64)
+    dev = device()
+    bufs = [torch.zeros((H, ld), dtype=torch.float32, device=dev) for _ in range(3)]
+    bufs[0][:, :W] = to_dev(w.astype(np.float32))
+    stream = torch.cuda.current_stream().cuda_stream
+    for T in (1, 4, 8):
+        say(f"adjoint strided T={T}")
+        _lib.call("sten_jacobi5_adjoint_f32", bufs[0].data_ptr(), bufs[1].data_ptr(), bufs[2].data_ptr(), H, W, ld,
+                  T, 0.25, stream)
+        got = to_host(bufs[1])[:, :W].astype(np.float64)
+        assert np.array_equal(got, oracle.jacobi5_adjoint(w, T)), f"T={T}"
+
+
+def test_adjoint_long_chain_within_bound(ag):
+    """T = 25 (five launches of the several-step kernel) on a grid with ragged tiles, within the FP32 bound."""
+    w = _w32(normal_grid(97, 517, seed=12))
+    say("adjoint T=25")
+    got = to_host(ag.adjoint(to_dev(w.astype(np.float32)), 25)).astype(np.float64)
+    ref = oracle.jacobi5_adjoint(w, 25)
+    assert np.all(np.abs(got - ref) <= oracle.bound_adjoint_fp32(w, 25))

@@ -49,22 +49,24 @@ def test_tb_bit_exact(ops, shape, dtype):
         ops.set_tb(0, 0, 0)
 
 
+@pytest.mark.parametrize("variant", [STREAM], ids=["stream"])
 @pytest.mark.parametrize("depth", [0, 4])
 @pytest.mark.parametrize("band", [1, 2, 7, 32, 1000])
-def test_tb_stream_band_and_depth(ops, band, depth):
+def test_tb_stream_band_and_depth(ops, band, depth, variant):
     """Band heights that leave a ragged last band, a band of one row, and one band for the whole grid;
     widths that give the right-aligned strip layout (multiple of the vector width, >= 64 vectors) and
     widths that do not."""
     cases = [((131, 300), np.float64), ((67, 1030), np.float32), ((40, 2049), np.float64),
-             ((29, 1032), np.float32), ((33, 128), np.float64), ((30, 256), np.float32)]
+             ((29, 1032), np.float32), ((33, 128), np.float64), ((30, 256), np.float32), ((45, 258), np.float64),
+             ((37, 1030), np.float64), ((21, 257), np.float64)]
     try:
-        ops.set_tb(STREAM, band, depth)
+        ops.set_tb(variant, band, depth)
         for shape, dtype in cases:
             u0 = normal_grid(*shape, seed=band + depth + shape[0], dtype=dtype)
             d = to_dev(u0)
             for levels in (1, 3, 5, 8, 10, 12):
                 T = 11
-                say(f"tb stream band={band} depth={depth} {shape} {dtype.__name__} levels={levels}")
+                say(f"tb variant={variant} band={band} depth={depth} {shape} {dtype.__name__} levels={levels}")
                 got = to_host(ops.jacobi5_tb(d, T, levels=levels))
                 assert np.array_equal(got, oracle.jacobi5(u0, T, dtype=dtype)), f"{shape} L={levels}"
     finally:
