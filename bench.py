@@ -480,9 +480,9 @@ def bench_tiled(ops, n: int, T: int, args, plain_sec_per_step: float, blocked_se
     want = ops.jacobi5(u0, T)
     comm = torch.cuda.Stream()
     res = {}
-    cases = ((2, 2, 1, "packed", True), (4, 4, 1, "packed", True), (2, 2, 12, "packed", True),
-             (2, 2, 12, "packed", False), (2, 2, 12, "direct", False), (4, 4, 12, "direct", False),
-             (8, 8, 12, "direct", False))
+    cases = ((2, 2, 1, "packed", True), (4, 4, 1, "packed", True), (2, 2, 1, "direct", False),
+             (4, 4, 1, "direct", False), (2, 2, 12, "packed", True), (2, 2, 12, "packed", False),
+             (2, 2, 12, "direct", False), (4, 4, 12, "direct", False), (8, 8, 12, "direct", False))
     for pr, pc, g, mode, two_streams in cases:
         t = ops.TiledGrid(n, n, pr, pc, comm_stream=comm if two_streams else None, ghost=g, exchange=mode)
         t.scatter(u0)
@@ -509,10 +509,11 @@ def bench_tiled(ops, n: int, T: int, args, plain_sec_per_step: float, blocked_se
         }
     res["workload"] = (f"{n}x{n} FP64 N(0,1) seed 0, {T} sweeps per step; pr x pc tiles with ghost frames of "
                        "depth g; exchange packed (pack + unpack kernels through send buffers) or direct (one "
-                       "copy kernel), on a second stream (2stream) or the compute stream (1stream); g = 1: one "
-                       "exchange and one sweep kernel per tile per sweep; g > 1: one exchange and one blocked "
-                       "launch over all tiles (per 32 tiles) per chunk of up to g sweeps, the sweeps split "
-                       "evenly over the chunks")
+                       "copy kernel), on a second stream (2stream, the paper's overlap scheme, with an event "
+                       "each way per exchange) or the compute stream (1stream); g = 1: one exchange and one "
+                       "sweep launch over all tiles (per 32 tiles) per sweep; g > 1: one exchange and one "
+                       "blocked launch over all tiles (per 32 tiles) per chunk of up to g sweeps, the sweeps "
+                       "split evenly over the chunks")
     return res
 
 
@@ -692,10 +693,12 @@ def bench_pressure_passes(n: int, reps: int, levels: int = 8) -> dict:
 
 
 def bench_adjoint(T: int, args) -> dict:
-    """Gradient workload: 1024x1024 FP32, L = sum(w * u_T), dL/du0 and dL/dc through autograd."""
+    """Gradient workload: 1024x1024 FP32, L = sum(w * u_T), dL/du0 and dL/dc through autograd; the forward
+    pass with recorded states and the reverse pass timed on the GPU; the transposed sweep per point against
+    the forward FP32 method at the same size and schedule kind."""
     import torch
 
-    from paper_2512_19851_amd import autograd
+    from paper_2512_19851_amd import _lib, autograd, ops
     from workloads import adjoint_f32
 
     log("[bench] adjoint")
@@ -704,6 +707,7 @@ def bench_adjoint(T: int, args) -> dict:
     w = torch.from_numpy(w_np.astype("float32")).to("cuda:0")
     c = torch.tensor(0.25, dtype=torch.float32, device="cuda:0", requires_grad=True)
     H, W = u0.shape
+    stream = torch.cuda.current_stream()
 
     def step():
         x = u0.detach().requires_grad_(True)
@@ -720,24 +724,56 @@ def bench_adjoint(T: int, args) -> dict:
         step()
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / reps
-    # transposed-sweep kernel alone: R steps without states
-    g = torch.randn_like(u0)
+
+    def timed(fn, r):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(r):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / r * 1e-3
+
+    # the two passes of the step on the GPU: forward recording u_0..u_T, reverse with dL/dc
+    states = torch.empty((T + 1, H, W), dtype=torch.float32, device=u0.device)
+    gin = torch.empty_like(u0)
+    work = torch.empty_like(u0)
+    parts = torch.empty(int(_lib.load().sten_adjoint_partials_len(H, W)), dtype=torch.float64, device=u0.device)
+    dc = torch.empty(1, dtype=torch.float64, device=u0.device)
+    sp = stream.cuda_stream
+    fwd_sec = timed(lambda: _lib.call("sten_jacobi5_f32_states", u0.data_ptr(), states.data_ptr(), H, W, W, T, 0.25,
+                                      sp), 20)
+
+    def reverse():
+        _lib.call("sten_jacobi5_adjoint_f32_seg", w.data_ptr(), states.data_ptr(), T, gin.data_ptr(),
+                  work.data_ptr(), parts.data_ptr(), 1, H, W, W, 0.25, sp)
+        _lib.call("sten_reduce_f64", parts.data_ptr(), parts.numel(), dc.data_ptr(), sp)
+
+    rev_sec = timed(reverse, 20)
+    # the transposed sweep without states (several per launch) against the forward FP32 method, per sweep
     R = args.kernel_reps
-    autograd.adjoint(g, 2, 0.25)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    autograd.adjoint(g, R, 0.25)
-    e1.record()
-    torch.cuda.synchronize()
-    per = e0.elapsed_time(e1) * 1e-3 / R
+    g = torch.randn_like(u0)
+    adj_sec = timed(lambda: autograd.adjoint(g, R, 0.25), 3) / R
+    fo, fw = torch.empty_like(u0), torch.empty_like(u0)
+    fwd_sweep_sec = timed(lambda: ops.jacobi5(u0, R, out=fo, work=fw), 3) / R
     return {
         "workload": f"{H}x{W} FP32 u0 N(0,1), w N(0,1) seed 0, T={T}: forward with recorded states + "
                     f"reverse pass (dL/du0 and dL/dc) per step",
         "ms_per_step": round(sec * 1e3, 4),
-        "adjoint_sweep_us": round(per * 1e6, 2),
-        "adjoint_sweep_GBps_at_8B": round(8.0 * H * W / per / 1e9, 1),
+        "forward_with_states_us": round(fwd_sec * 1e6, 2),
+        "reverse_with_dc_us": round(rev_sec * 1e6, 2),
+        "reverse_vs_forward": round(rev_sec / fwd_sec, 3),
+        "adjoint_sweep_us": round(adj_sec * 1e6, 3),
+        "forward_fp32_sweep_us": round(fwd_sweep_sec * 1e6, 3),
+        "adjoint_vs_forward_per_point": round(adj_sec / fwd_sweep_sec, 3),
+        "adjoint_sweep_GBps_at_8B": round(8.0 * H * W / adj_sec / 1e9, 1),
+        "note": "ms_per_step: wall time of autograd forward + backward (Python and allocations included); "
+                "forward_with_states_us / reverse_with_dc_us: HIP events around the library calls alone; "
+                f"adjoint_sweep_us and forward_fp32_sweep_us: {R} sweeps in one call each (several sweeps "
+                "per launch in both), divided by the sweeps",
         "tolerance": "dL/du0 within the FP32 bound of the FP64 oracle gradient and of central FD "
                      "(h=1e-6) at 64 coordinates; dL/dc within its bound (parity tests)",
     }

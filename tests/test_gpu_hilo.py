@@ -34,7 +34,8 @@ def _crafted(n=64, seed=0):
     return u
 
 
-@pytest.mark.parametrize("shape", [(1, 1), (3, 3), (64, 64), (37, 129), (130, 1030)], ids=str)
+@pytest.mark.parametrize("shape", [(1, 1), (3, 3), (64, 64), (37, 129), (130, 1030), (36, 1028), (9, 4100)],
+                         ids=str)
 def test_encode_decode_bit_exact(ops, shape):
     u = _crafted(max(shape), seed=shape[1])[: shape[0], : shape[1]].copy()
     say(f"encode {shape}")
@@ -44,6 +45,24 @@ def test_encode_decode_bit_exact(ops, shape):
     assert np.array_equal(to_host(g.q()), q_want)
     say(f"decode {shape}")
     assert np.array_equal(to_host(ops.hilo_decode(g)), oracle.hilo_decode(hi_want, q_want))
+
+
+def test_encode_decode_strided_vector_rows(ops):
+    """Row stride a multiple of 4 with widths that are not (the vector kernels' ragged last lanes), and a
+    stride that is not (the element-wise kernels), each bit-exact with the oracle's encoding."""
+    import torch
+
+    for (H, W, ld) in [(7, 1027, 1028), (5, 2050, 2052), (6, 1021, 1023)]:
+        u = _crafted(max(H, W), seed=W)[:H, :W].copy()
+        x = torch.zeros((H, ld), dtype=torch.float64, device=device())[:, :W]
+        x.copy_(to_dev(u))
+        say(f"encode strided {H}x{W} ld={ld}")
+        g = ops.hilo_encode(x)
+        hi_want, q_want = oracle.hilo_encode(u)
+        assert np.array_equal(to_host(g.hi())[:, :W].view(np.uint32), hi_want.view(np.uint32))
+        assert np.array_equal(to_host(g.q())[:, :W], q_want)
+        out = torch.zeros((H, ld), dtype=torch.float64, device=device())[:, :W]
+        assert np.array_equal(to_host(ops.hilo_decode(g, out=out)), oracle.hilo_decode(hi_want, q_want))
 
 
 SHAPES = [(3, 3), (5, 7), (64, 64), (63, 65), (257, 1031), (600, 3), (3, 600), (130, 2049)]
