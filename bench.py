@@ -790,7 +790,8 @@ def main() -> int:
     ap.add_argument("--cpu-budget", type=float, default=16.0, help="seconds of CPU oracle work")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extensions", action="store_true")
-    ap.add_argument("--mode", choices=["step", "sweep", "copy", "hilo", "tb", "cavity", "pressure", "batch"],
+    ap.add_argument("--mode", choices=["step", "sweep", "copy", "hilo", "tb", "cavity", "pressure", "batch", "adjoint",
+                                       "tiled", "mixed"],
                     default="step",
                     help="step: the benchmark; sweep: only --kernel-reps sweep launches; "
                          "copy: only --kernel-reps plain grid copies (counter calibration); "
@@ -798,7 +799,10 @@ def main() -> int:
                          "tb: only --kernel-reps temporally blocked launches; "
                          "cavity: only the cavity-flow extension (--n grid side); "
                          "pressure: only --kernel-reps blocked passes of 8 cavity pressure iterations (--n); "
-                         "batch: only the batched extension (--sweeps, --steps graph replays)")
+                         "batch: only the batched extension (--sweeps, --steps graph replays); "
+                         "adjoint: only the gradient extension (1024^2, T = 10); "
+                         "tiled: only the tiled extension (--n, --sweeps); "
+                         "mixed: only the hi/lo extension (--n, --sweeps; timed against one sweep per launch)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -825,6 +829,34 @@ def main() -> int:
         from paper_2512_19851_amd import ops
 
         print(json.dumps({"mode": "batch", **bench_batch(ops, args.sweeps, args)}), flush=True)
+        return 0
+    if args.mode == "adjoint":
+        print(json.dumps({"mode": "adjoint", **bench_adjoint(10, args)}), flush=True)
+        return 0
+    if args.mode in ("tiled", "mixed"):
+        n, T = args.n, args.sweeps
+        u0 = torch.from_numpy(large_f64(0, n)).to(dev)
+        o, w = torch.empty_like(u0), torch.empty_like(u0)
+        ops.jacobi5(u0, T, out=o, work=w)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ops.jacobi5(u0, T, out=o, work=w)
+        torch.cuda.synchronize()
+        blocked = time.perf_counter() - t0
+        ops.set_schedule(1)
+        ops.jacobi5(u0, T, out=o, work=w)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ops.jacobi5(u0, T, out=o, work=w)
+        torch.cuda.synchronize()
+        single = time.perf_counter() - t0
+        ops.set_schedule(0)
+        del u0, o, w
+        if args.mode == "tiled":
+            res = bench_tiled(ops, n, T, args, single, blocked)
+        else:
+            res = bench_mixed(ops, n, T, args, single, blocked)
+        print(json.dumps({"mode": args.mode, **res}), flush=True)
         return 0
     n, T = args.n, args.sweeps
     log(f"[bench] generating {n}x{n} FP64 N(0,1) seed 0")
