@@ -27,6 +27,7 @@
 #include <mutex>
 #include <sstream>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "common.hpp"
@@ -203,13 +204,14 @@ __device__ __host__ inline RegShape reg_shape(int H, int W, int block) {
 // LDS floats of the row exchange area (both parities, first and last row of every wave).
 __device__ __host__ inline int reg_lds_floats(const RegShape& s, int block) { return 2 * 2 * (block / 64) * 64 * s.V; }
 
+// DPP wave shifts with bound control set: the lane without a source (lane 0,
+// resp. 63) reads 0, so no register has to be cleared first and the shift can
+// fold into the add that consumes it.
 __device__ __forceinline__ float dpp_from_lower_lane(float v) {  // lane l receives lane l-1
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xF, 0xF,
-                                                                 false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138, 0xF, 0xF, true));
 }
 __device__ __forceinline__ float dpp_from_upper_lane(float v) {  // lane l receives lane l+1
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xF, 0xF,
-                                                                 false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xF, 0xF, true));
 }
 
 template <int V, int R>
@@ -217,7 +219,7 @@ __device__ __forceinline__ void run_reg(const Desc& d, int T, float c, float* ld
     const int H = d.H, W = d.W;
     const int64_t ld = d.ld;
     const int nw = blockDim.x >> 6;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int i0 = wave * R;
     const int j0 = lane * V;
@@ -244,32 +246,51 @@ __device__ __forceinline__ void run_reg(const Desc& d, int T, float c, float* ld
         lds[o_last + e] = v[R - 1][e];
     }
     __syncthreads();
-    for (int t = 0; t < T; ++t) {
-        const float* cur_h = lds + (t & 1) * half;
-        float* nxt_h = lds + ((t + 1) & 1) * half;
-        float prev[V], below[V];
+    // One sweep in either row order. Downward, each row's new values replace its
+    // old ones once the next row has read them (kept in `prev`); upward, the same
+    // with `next`. Two sweeps in opposite orders per loop iteration let every
+    // loop-carried row end in the register it started in (a single direction
+    // shifts the rows by one register row per sweep, paid for with copies).
+    auto sweep = [&](const float* cur_h, float* nxt_h, auto down) {
+        // Re-read the wave's first row each sweep, so that the R x V point masks below are
+        // formed in the loop by scalar instructions: hoisted out of it, they need more
+        // SGPRs than there are and spill to VGPR lanes that every sweep reads back.
+        int i0_t = i0;
+        asm volatile("" : "+s"(i0_t));
+        float above[V], below[V];
 #pragma unroll
         for (int e = 0; e < V; ++e) {
-            prev[e] = (wave > 0) ? cur_h[o_above + e] : 0.0f;
+            above[e] = (wave > 0) ? cur_h[o_above + e] : 0.0f;
             below[e] = (wave + 1 < nw) ? cur_h[o_below + e] : 0.0f;
         }
+        float carry[V];  // old values of the row just updated (above it when downward, below when upward)
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const int i = i0 + k;
+        for (int e = 0; e < V; ++e) carry[e] = down ? above[e] : below[e];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int k = down ? q : R - 1 - q;
+            const int i = i0_t + k;
             const bool row_in = (i >= 1) && (i <= H - 2);
             const float lft = dpp_from_lower_lane(v[k][V - 1]);  // column j0 - 1
             const float rgt = dpp_from_upper_lane(v[k][0]);      // column j0 + V
             float nv[V];
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-                const float dn = (k == R - 1) ? below[e] : v[k + 1 < R ? k + 1 : k][e];
+                float up, dn;
+                if (down) {
+                    up = carry[e];
+                    dn = (k == R - 1) ? below[e] : v[k + 1 < R ? k + 1 : k][e];
+                } else {
+                    up = (k == 0) ? above[e] : v[k > 0 ? k - 1 : 0][e];
+                    dn = carry[e];
+                }
                 const float w_ = (e == 0) ? lft : v[k][e > 0 ? e - 1 : 0];
                 const float e_ = (e == V - 1) ? rgt : v[k][e < V - 1 ? e + 1 : 0];
-                nv[e] = (row_in && col_in[e]) ? stencil(prev[e], dn, w_, e_, c) : v[k][e];
+                nv[e] = (row_in && col_in[e]) ? stencil(up, dn, w_, e_, c) : v[k][e];
             }
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-                prev[e] = v[k][e];
+                carry[e] = v[k][e];
                 v[k][e] = nv[e];
             }
         }
@@ -279,7 +300,13 @@ __device__ __forceinline__ void run_reg(const Desc& d, int T, float c, float* ld
             nxt_h[o_last + e] = v[R - 1][e];
         }
         __syncthreads();
+    };
+    int t = 0;
+    for (; t + 1 < T; t += 2) {
+        sweep(lds, lds + half, std::true_type{});
+        sweep(lds + half, lds, std::false_type{});
     }
+    if (t < T) sweep(lds, lds + half, std::true_type{});
 #pragma unroll
     for (int k = 0; k < R; ++k)
 #pragma unroll

@@ -26,7 +26,7 @@ def ops():
 
 
 MIXED_SHAPES = [(1, 1), (2, 5), (5, 2), (3, 3), (16, 16), (17, 33), (64, 64), (100, 257), (256, 255), (300, 250),
-                (3, 700), (700, 3), (45, 61), (128, 130)]
+                (3, 700), (700, 3), (45, 61), (128, 130), (150, 180), (190, 129), (33, 200)]
 
 
 def _check(outs, u0s, T):
