@@ -475,6 +475,11 @@ sten_status sten_jacobi5_adjoint_f32_seg(const float* lam_in, const float* state
                                          float* lam_out, float* work, double* partials, int32_t reset,
                                          int64_t H, int64_t W, int64_t ld, float c, hipStream_t stream);
 
+/* Tuning hook of the transposed steps without dL/dc: transposed steps per
+ * launch of the several-step kernel (1..8; 0 restores the built-in choice).
+ * Results unchanged. STEN_ERR_ARG otherwise. */
+sten_status sten_tune_adjoint_levels(int32_t levels);
+
 /* *out = sum of partials[0..n) in a fixed order (one workgroup). */
 sten_status sten_reduce_f64(const double* partials, int64_t n, double* out, hipStream_t stream);
 

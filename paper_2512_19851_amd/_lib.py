@@ -100,6 +100,7 @@ SIGNATURES = {
     "sten_cavity_pressure_f64": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _i64, _i64, _i32, _f64, _f64, _f64, _i32,
                                                 _vp]),
     "sten_tune_pressure": (ctypes.c_int, [_i32]),
+    "sten_tune_adjoint_levels": (ctypes.c_int, [_i32]),
     "sten_tiled_workspace_bytes_ex": (_sz, [_i64, _i64, _i32, _i32, _i32, _i32]),
     "sten_tiled_create_ex": (ctypes.c_int, [_i64, _i64, _i32, _i32, _i32, _i32, _vp, _sz, ctypes.POINTER(_vp)]),
     "sten_tiled_plan_check": (ctypes.c_int, [_i64, _i64, _i32, _i32, _i32, _i32, ctypes.POINTER(ctypes.c_int64),

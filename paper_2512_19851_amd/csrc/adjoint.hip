@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 
 #include "common.hpp"
@@ -34,8 +35,6 @@ namespace {
 
 constexpr int kAdjBlock = 256;
 constexpr int kAdjRows = 2;       // rows per tile of the fused one-step kernel
-constexpr int kAdjTbRows = 4;     // output rows per tile of the several-step kernel
-constexpr int kAdjMaxLevels = 4;  // transposed steps per launch of the several-step kernel
 
 constexpr int kAdjTileBlock = kWave;  // one wave (256 columns) per workgroup of the fused one-step kernel
 
@@ -208,87 +207,220 @@ __global__ __launch_bounds__(kAdjTileBlock) void adjoint_tile_kernel(const float
     }
 }
 
-// TL transposed steps per launch (no dL/dc), the register-tile form of
-// temporal blocking: a wave loads a tile of ROWS + 2*TL rows by 256 columns
-// (4 floats per lane; zeros outside the grid) and applies TL steps in
-// registers. After step s the values are exact on the tile shrunk by s on
-// every side (a point needs only its four neighbours of the step before), so
-// the central ROWS rows by 256 - 2*HALO columns (HALO = TL rounded up to a
-// multiple of 4) are exact after TL steps and stored. Points outside the grid
-// are never interior, so they never feed a value; they are never stored.
-// INNER: every loaded point is an interior point, so no term is masked and no
-// point is on the ring: the step is the plain five-point expression.
-template <int ROWS, int TL, bool VEC, bool INNER>
-__device__ __forceinline__ void adjoint_tb_tile(const float* __restrict__ g, float* __restrict__ out, int H, int W,
-                                                int64_t ld, float c, int cs, int r0) {
-    using stream::lane_from_lower;
-    using stream::lane_from_upper;
-    constexpr int NR = ROWS + 2 * TL;
-    constexpr int HALO = (TL + kAdjV - 1) / kAdjV * kAdjV;
-    constexpr int OW = kWave * kAdjV - 2 * HALO;
-    const int j0 = cs + (int)threadIdx.x * kAdjV;
-    float a[NR][kAdjV];
+// Several transposed steps per launch (no dL/dc): the streaming form of
+// temporal blocking, as in the forward kernel. One wave owns a strip of 256
+// loaded columns (4 floats per lane) and a band of output rows, and walks the
+// band once: each step loads one row (level 0) and, for s = 1..TL, computes
+// level s of the row s behind the loaded one from the two level-(s-1) rows it
+// keeps and the level-(s-1) row just produced; level TL of the row TL behind
+// is stored. Bands cover every row and strips every column, ring included,
+// since the transposed step writes every point. A level's row r is computed
+// from rows a (r - dir, kept from the step before) and b (r + dir), so a + b
+// is N + S or S + N: the same bits, IEEE addition being commutative (a
+// missing term is an exact zero either way).
+//
+// Rows and columns outside the grid are loaded clamped to the grid, and the
+// strip's halo columns see a zero past the wave's edge lanes: none of these
+// points is interior, so the masked expression never lets their values reach
+// a point (and plain groups, see below, never hold such points next to a
+// stored one: the halo is at least TL columns wide, and the rows a plain group
+// computes all lie in [2, H-3]). In a group whose level rows all lie in
+// [2, H-3], on a strip whose loaded columns all lie in [2, W-3], every point
+// and its four neighbours are interior, so the plain five-point expression is
+// the transposed step there; elsewhere every term is masked.
+constexpr int kAdjStreamA = 4;       // rows loaded ahead
+constexpr int kAdjStreamLevels = 8;  // transposed steps per launch at most
+
+// Tuning setting (read once per call; every accepted value gives the same bits):
+// transposed steps per launch, 0 for the built-in choice.
+std::atomic<int> g_adj_levels{0};
+
+template <int A>
+struct AdjRing {
+    static constexpr int P = A + 2;
+    static constexpr int U = (P % 3 == 0) ? P : 3 * P;  // steps per group: whole periods of every rotation
+};
+
+// One level of the row r = (loaded row) - dir*s: a = row r - dir, m = row r, b = row r + dir.
+template <bool MASK>
+__device__ __forceinline__ void adj_stream_level(const float (&a)[kAdjV], const float (&m)[kAdjV],
+                                                 const float (&b)[kAdjV], float (&res)[kAdjV], float c, int r,
+                                                 int dir, int H, const AdjCol (&col)[kAdjV]) {
+    const float lft = stream::lane_from_lower(m[kAdjV - 1]);  // column j0 - 1
+    const float rgt = stream::lane_from_upper(m[0]);          // column j0 + 4
+    if constexpr (!MASK) {
 #pragma unroll
-    for (int k = 0; k < NR; ++k) adj_load<VEC>(g, r0 + k, H, W, ld, j0, a[k]);
-    AdjCol col[kAdjV];
-#pragma unroll
-    for (int e = 0; e < kAdjV; ++e) col[e] = adj_col(j0 + e, W);
-#pragma unroll
-    for (int s = 1; s <= TL; ++s) {
-        // rows s-1 .. NR-s are exact; update rows s .. NR-1-s in place, top to bottom
-        float prev[kAdjV];
-#pragma unroll
-        for (int e = 0; e < kAdjV; ++e) prev[e] = a[s - 1][e];
-#pragma unroll
-        for (int k = s; k <= NR - 1 - s; ++k) {
-            const int r = r0 + k;
-            const float lft = lane_from_lower(a[k][kAdjV - 1]);
-            const float rgt = lane_from_upper(a[k][0]);
-            float nv[kAdjV];
-#pragma unroll
-            for (int e = 0; e < kAdjV; ++e) {
-                const float w = e == 0 ? lft : a[k][e > 0 ? e - 1 : 0];
-                const float ea = e == kAdjV - 1 ? rgt : a[k][e < kAdjV - 1 ? e + 1 : 0];
-                if constexpr (INNER) {
-                    float t = prev[e] + a[k + 1][e];
-                    t = t + w;
-                    t = t + ea;
-                    nv[e] = c * t;
-                } else {
-                    nv[e] = adj_point(prev[e], a[k + 1][e], w, ea, a[k][e], adj_interior_row(r - 1, H),
-                                      adj_interior_row(r + 1, H), adj_interior_row(r, H), col[e], c);
-                }
-            }
-#pragma unroll
-            for (int e = 0; e < kAdjV; ++e) {
-                prev[e] = a[k][e];
-                a[k][e] = nv[e];
-            }
+        for (int e = 0; e < kAdjV; ++e) {
+            const float w = e == 0 ? lft : m[e > 0 ? e - 1 : 0];
+            const float ea = e == kAdjV - 1 ? rgt : m[e < kAdjV - 1 ? e + 1 : 0];
+            float t = a[e] + b[e];
+            t = t + w;
+            t = t + ea;
+            res[e] = c * t;
         }
-    }
-    const int lo = max(cs + HALO, 0), hi = min(cs + HALO + OW, W);
+    } else {
+        const bool ia = adj_interior_row(r - dir, H), ib = adj_interior_row(r + dir, H), rin = adj_interior_row(r, H);
 #pragma unroll
-    for (int k = TL; k < TL + ROWS; ++k) {
-        const int r = r0 + k;
-        if (r >= 0 && r < H) adj_store<VEC>(out, r, ld, j0, lo, hi, a[k]);
+        for (int e = 0; e < kAdjV; ++e) {
+            const float w = e == 0 ? lft : m[e > 0 ? e - 1 : 0];
+            const float ea = e == kAdjV - 1 ? rgt : m[e < kAdjV - 1 ? e + 1 : 0];
+            res[e] = adj_point(a[e], b[e], w, ea, m[e], ia, ib, rin, col[e], c);
+        }
     }
 }
 
-template <int ROWS, int TL, bool VEC>
-__global__ __launch_bounds__(kWave) void adjoint_tb_kernel(const float* __restrict__ g, float* __restrict__ out,
-                                                           int H, int W, int64_t ld, float c, uint32_t strips) {
+// One step: the level-0 row L (x) enters; levels 1..NACT advance by one row each.
+template <int TL, int NACT, bool MASK>
+__device__ __forceinline__ void adj_stream_step(float (&w0)[TL][kAdjV], float (&w1)[TL][kAdjV],
+                                                const float (&a0)[kAdjV], const float (&b0)[kAdjV],
+                                                const float (&x)[kAdjV], float (&top)[kAdjV], int L, int dir, int H,
+                                                float c, const AdjCol (&col)[kAdjV]) {
+    if constexpr (NACT >= 1) {
+        float cur[kAdjV];
+        adj_stream_level<MASK>(a0, b0, x, cur, c, L - dir, dir, H, col);
+#pragma unroll
+        for (int s = 2; s <= NACT; ++s) {
+            float nv[kAdjV];
+            adj_stream_level<MASK>(w0[s - 1], w1[s - 1], cur, nv, c, L - dir * s, dir, H, col);
+#pragma unroll
+            for (int e = 0; e < kAdjV; ++e) {
+                w0[s - 1][e] = w1[s - 1][e];
+                w1[s - 1][e] = cur[e];
+                cur[e] = nv[e];
+            }
+        }
+        if constexpr (NACT < TL) {
+#pragma unroll
+            for (int e = 0; e < kAdjV; ++e) {
+                w0[NACT][e] = w1[NACT][e];
+                w1[NACT][e] = cur[e];
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < kAdjV; ++e) top[e] = cur[e];
+        }
+    }
+}
+
+// Steps 0 .. 2*TL-1: level s is complete from step 2s on. `plain`: every row these steps compute
+// lies in [2, H-3] on a strip of interior columns.
+template <int TL, int A, int K, int EDGE>
+__device__ __forceinline__ void adj_stream_prologue(float (&w0)[TL][kAdjV], float (&w1)[TL][kAdjV],
+                                                    float (&ring)[AdjRing<A>::P][kAdjV], const float* __restrict__ g,
+                                                    int L0, int dir, int H, int W, int64_t ld, int j0, float c,
+                                                    const AdjCol (&col)[kAdjV], bool plain) {
+    constexpr int P = AdjRing<A>::P;
+    if constexpr (K < 2 * TL) {
+        float unused[kAdjV];
+        if (plain)
+            adj_stream_step<TL, K / 2, false>(w0, w1, ring[(K + P - 2) % P], ring[(K + P - 1) % P], ring[K % P],
+                                              unused, L0 + dir * K, dir, H, c, col);
+        else
+            adj_stream_step<TL, K / 2, true>(w0, w1, ring[(K + P - 2) % P], ring[(K + P - 1) % P], ring[K % P],
+                                             unused, L0 + dir * K, dir, H, c, col);
+        stream::stream_load<float, kAdjV, EDGE>(g, L0 + dir * (K + A), H, W, ld, j0, ring[(K + A) % P]);
+        __builtin_amdgcn_sched_barrier(0);
+        adj_stream_prologue<TL, A, K + 1, EDGE>(w0, w1, ring, g, L0, dir, H, W, ld, j0, c, col, plain);
+    }
+}
+
+// One wave's band [rb, re) of a strip loading columns [cs, cs + 256) and storing [olo, ohi).
+// EDGE 0: loaded columns all in [2, W-3], whole-vector loads and stores; EDGE 1: loaded columns
+// inside the grid, whole-vector loads and stores, masked terms everywhere; EDGE 2: clamped loads,
+// masked terms everywhere, stores column by column.
+template <int TL, int A, int EDGE>
+__device__ __forceinline__ void adj_stream_band(const float* __restrict__ g, float* __restrict__ out, int H, int W,
+                                                int64_t ld, float c, int cs, int olo, int ohi, int rb, int re,
+                                                int dir) {
+    constexpr int P = AdjRing<A>::P;
+    constexpr int U = AdjRing<A>::U;
+    const int j0 = cs + (int)threadIdx.x * kAdjV;
+    AdjCol col[kAdjV];
+#pragma unroll
+    for (int e = 0; e < kAdjV; ++e) col[e] = adj_col(j0 + e, W);
+    const bool st_lane = (j0 >= olo) && (j0 + kAdjV <= ohi);
+    const uint32_t voff_vec = st_lane ? (uint32_t)j0 * 4u : stream::kDropOffset;
+    uint32_t voff_el[kAdjV];
+#pragma unroll
+    for (int e = 0; e < kAdjV; ++e)
+        voff_el[e] = (j0 + e >= olo && j0 + e < ohi) ? (uint32_t)(j0 + e) * 4u : stream::kDropOffset;
+
+    const int L0 = dir > 0 ? rb - TL : re - 1 + TL;
+    const int nsteps = (re - rb) + 2 * TL;
+    float w0[TL][kAdjV], w1[TL][kAdjV];
+    float ring[P][kAdjV];
+#pragma unroll
+    for (int i = 0; i < A; ++i) stream::stream_load<float, kAdjV, EDGE>(g, L0 + dir * i, H, W, ld, j0, ring[i]);
+    {
+        // the prologue's level rows lie in [min(L0, Le) - TL, max(L0, Le) + TL], Le its last loaded row
+        const int Le = L0 + dir * (2 * TL - 1);
+        const bool plain = EDGE == 0 && min(L0, Le) - TL >= 2 && max(L0, Le) + TL <= H - 3;
+        adj_stream_prologue<TL, A, 0, EDGE>(w0, w1, ring, g, L0, dir, H, W, ld, j0, c, col, plain);
+    }
+
+    const int ngroups = (nsteps - 2 * TL + U - 1) / U;
+    for (int k = 0; k < ngroups; ++k) {
+        const int gs = 2 * TL + k * U;
+        const int La = L0 + dir * gs, Lb = L0 + dir * (gs + U - 1);
+        // the level rows of this group lie in [min(La, Lb) - TL, max(La, Lb) + TL]
+        const bool plain = EDGE == 0 && min(La, Lb) - TL >= 2 && max(La, Lb) + TL <= H - 3;
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            const int t = 2 * TL + i;  // step index modulo U
+            const int L = L0 + dir * (gs + i);
+            float top[kAdjV];
+            if (plain)
+                adj_stream_step<TL, TL, false>(w0, w1, ring[(t + P - 2) % P], ring[(t + P - 1) % P], ring[t % P], top,
+                                               L, dir, H, c, col);
+            else
+                adj_stream_step<TL, TL, true>(w0, w1, ring[(t + P - 2) % P], ring[(t + P - 1) % P], ring[t % P], top,
+                                              L, dir, H, c, col);
+            stream::stream_load<float, kAdjV, EDGE>(g, L + dir * A, H, W, ld, j0, ring[(t + A) % P]);
+            stream::stream_store<float, kAdjV, EDGE>(out, L - dir * TL, ld, W, gs + i < nsteps, voff_vec, voff_el,
+                                                     top);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+// Strip layout. Flush (flush != 0: 16-byte aligned rows, W a multiple of 4 and at least 256):
+// strip 0 loads columns [0, 256) and stores [0, 256 - HALO); strip k loads from k*OW and stores
+// [k*OW + HALO, (k+1)*OW + HALO); the last strip loads the grid's last 256 columns and stores
+// [W - 256 + HALO, W). Every load stays inside the grid, and the last strip's stores may overlap
+// its neighbour's with the same bits. Otherwise strip k loads from k*OW - HALO and stores [k*OW,
+// (k+1)*OW) within the grid. Band b covers rows [b*band, (b+1)*band) within the grid; even bands
+// walk down, odd bands up.
+// Occupancy: 4 waves per SIMD (128 VGPRs) up to 5 levels, 3 (168) above; uncapped, the masked path's
+// registers would hold the 8-level kernel to 2 waves per SIMD.
+template <int TL, int A>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(TL <= 5 ? 4 : 3))) void adjoint_stream_kernel(const float* __restrict__ g, float* __restrict__ out,
+                                                               int H, int W, int64_t ld, float c, uint32_t strips,
+                                                               int band, int flush) {
     constexpr int HALO = (TL + kAdjV - 1) / kAdjV * kAdjV;
     constexpr int OW = kWave * kAdjV - 2 * HALO;
     const uint32_t tile = xcd_tile_of_block(blockIdx.x, gridDim.x);
-    const uint32_t band = tile / strips;
-    const uint32_t strip = tile - band * strips;
-    const int cs = (int)strip * OW - HALO;  // first loaded column
-    const int r0 = (int)band * ROWS - TL;   // first loaded row
-    const bool inner = r0 >= 1 && r0 + ROWS + 2 * TL <= H - 1 && cs >= 1 && cs + kWave * kAdjV <= W - 1;
-    if (inner)
-        adjoint_tb_tile<ROWS, TL, VEC, true>(g, out, H, W, ld, c, cs, r0);
+    const uint32_t bi = tile / strips;
+    const uint32_t strip = tile - bi * strips;
+    int cs, olo, ohi;
+    if (flush) {
+        const bool last = strip == strips - 1;
+        cs = last ? W - kWave * kAdjV : (int)strip * OW;
+        olo = strip == 0 ? 0 : cs + HALO;
+        ohi = last ? W : cs + HALO + OW;
+    } else {
+        cs = (int)strip * OW - HALO;
+        olo = max(cs + HALO, 0);
+        ohi = min(cs + HALO + OW, W);
+    }
+    const int rb = (int)bi * band;
+    const int re = min(rb + band, H);
+    const int dir = (bi & 1) ? -1 : 1;
+    if (flush && cs >= 2 && cs + kWave * kAdjV <= W - 2)
+        adj_stream_band<TL, A, 0>(g, out, H, W, ld, c, cs, olo, ohi, rb, re, dir);
+    else if (flush)
+        adj_stream_band<TL, A, 1>(g, out, H, W, ld, c, cs, olo, ohi, rb, re, dir);
     else
-        adjoint_tb_tile<ROWS, TL, VEC, false>(g, out, H, W, ld, c, cs, r0);
+        adj_stream_band<TL, A, 2>(g, out, H, W, ld, c, cs, olo, ohi, rb, re, dir);
 }
 
 __global__ void fill_f64_kernel(double* p, int64_t n, double v) {
@@ -361,23 +493,45 @@ void launch_adjoint_step(const float* g, const float* u, float* out, double* par
                                                                               c, adj_tiles_x(W));
 }
 
-template <int TL, bool VEC>
-void launch_adjoint_tb_levels(const float* g, float* out, int H, int W, int64_t ld, float c, hipStream_t s) {
-    constexpr int HALO = (TL + kAdjV - 1) / kAdjV * kAdjV;
-    constexpr int OW = kWave * kAdjV - 2 * HALO;
-    const uint32_t strips = ceil_div(W, OW);
-    const uint32_t bands = ceil_div(H, kAdjTbRows);
-    adjoint_tb_kernel<kAdjTbRows, TL, VEC><<<strips * bands, kWave, 0, s>>>(g, out, H, W, ld, c, strips);
+// Waves of one kernel that fit on the device at once (one wave per workgroup).
+int adj_resident_waves(const void* kernel) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWave, 0) != hipSuccess)
+        return 0;
+    return cus * per_cu;
 }
 
-// One launch of `levels` transposed steps (1..kAdjMaxLevels) from g into out.
-template <bool VEC>
-void launch_adjoint_tb(const float* g, float* out, int H, int W, int64_t ld, float c, int levels, hipStream_t s) {
+template <int TL>
+void launch_adjoint_stream_levels(const float* g, float* out, int H, int W, int64_t ld, float c, bool vec,
+                                  hipStream_t s) {
+    constexpr int HALO = (TL + kAdjV - 1) / kAdjV * kAdjV;
+    constexpr int OW = kWave * kAdjV - 2 * HALO;
+    const bool flush = vec && W % kAdjV == 0 && W >= kWave * kAdjV;
+    const uint32_t strips = flush ? ceil_div(W - kWave * kAdjV, OW) + 1 : ceil_div(W, OW);
+    // the tallest bands that still give every resident wave slot a band, and at least 2*TL rows
+    static const int waves =
+        adj_resident_waves(reinterpret_cast<const void*>(&adjoint_stream_kernel<TL, kAdjStreamA>));
+    const int64_t fit = std::max<int64_t>(1, (waves > 0 ? waves : 1024) / (int64_t)strips);
+    const int band = (int)std::max<int64_t>(2 * TL, (H + fit - 1) / fit);
+    const uint32_t bands = ceil_div(H, band);
+    adjoint_stream_kernel<TL, kAdjStreamA><<<strips * bands, kWave, 0, s>>>(g, out, H, W, ld, c, strips, band,
+                                                                             flush ? 1 : 0);
+}
+
+// One launch of `levels` transposed steps (1..kAdjStreamLevels) from g into out.
+void launch_adjoint_stream(const float* g, float* out, int H, int W, int64_t ld, float c, int levels, bool vec,
+                           hipStream_t s) {
     switch (levels) {
-        case 1: launch_adjoint_tb_levels<1, VEC>(g, out, H, W, ld, c, s); break;
-        case 2: launch_adjoint_tb_levels<2, VEC>(g, out, H, W, ld, c, s); break;
-        case 3: launch_adjoint_tb_levels<3, VEC>(g, out, H, W, ld, c, s); break;
-        default: launch_adjoint_tb_levels<4, VEC>(g, out, H, W, ld, c, s); break;  // levels == 4
+        case 1: launch_adjoint_stream_levels<1>(g, out, H, W, ld, c, vec, s); break;
+        case 2: launch_adjoint_stream_levels<2>(g, out, H, W, ld, c, vec, s); break;
+        case 3: launch_adjoint_stream_levels<3>(g, out, H, W, ld, c, vec, s); break;
+        case 4: launch_adjoint_stream_levels<4>(g, out, H, W, ld, c, vec, s); break;
+        case 5: launch_adjoint_stream_levels<5>(g, out, H, W, ld, c, vec, s); break;
+        case 6: launch_adjoint_stream_levels<6>(g, out, H, W, ld, c, vec, s); break;
+        case 7: launch_adjoint_stream_levels<7>(g, out, H, W, ld, c, vec, s); break;
+        default: launch_adjoint_stream_levels<8>(g, out, H, W, ld, c, vec, s); break;  // levels == 8
     }
 }
 
@@ -440,15 +594,17 @@ sten_status adjoint_seg(const float* lam_in, const float* states, int32_t nsteps
     }
     // no dL/dc: several steps per launch, the steps split as evenly as the launch count allows; the
     // last launch writes lam_out
-    const int launches = (nsteps + kAdjMaxLevels - 1) / kAdjMaxLevels;
+    // built-in: 3 steps per launch on grids of up to 2^23 points, where the 2*TL-row bands of deeper
+    // launches leave most wave slots empty (us per step at 3 / 4 / 8 steps per launch: 1024^2 2.2 /
+    // 3.0 / 3.7, 2048^2 3.2 / 4.0 / 4.5), and 8 above (4096^2: 6.7 at 8, 7.7 at 4, 10.0 at 3)
+    const int tuned = g_adj_levels.load(std::memory_order_relaxed);
+    const int per_launch = tuned > 0 ? tuned : (H * W <= ((int64_t)1 << 23) ? 3 : kAdjStreamLevels);
+    const int launches = (nsteps + per_launch - 1) / per_launch;
     const int base = nsteps / launches, extra = nsteps % launches;
     for (int k = 1; k <= launches; ++k) {
         const int lev = base + (k <= extra ? 1 : 0);
         float* dst = ((launches - k) % 2 == 0) ? lam_out : work;
-        if (vec)
-            launch_adjoint_tb<true>(src, dst, h, w, ld, c, lev, stream);
-        else
-            launch_adjoint_tb<false>(src, dst, h, w, ld, c, lev, stream);
+        launch_adjoint_stream(src, dst, h, w, ld, c, lev, vec, stream);
         src = dst;
     }
     return check_launch();
@@ -528,6 +684,12 @@ sten_status sten_jacobi5_adjoint_f32_seg(const float* lam_in, const float* state
 sten_status sten_jacobi5_adjoint_f32(const float* gout, float* gin, float* work, int64_t H, int64_t W, int64_t ld,
                                      int32_t T, float c, hipStream_t stream) {
     return sten_jacobi5_adjoint_f32_seg(gout, nullptr, T, gin, work, nullptr, 0, H, W, ld, c, stream);
+}
+
+sten_status sten_tune_adjoint_levels(int32_t levels) {
+    if (levels < 0 || levels > sten::kAdjStreamLevels) return STEN_ERR_ARG;
+    sten::g_adj_levels.store(levels, std::memory_order_relaxed);
+    return STEN_OK;
 }
 
 sten_status sten_reduce_f64(const double* partials, int64_t n, double* out, hipStream_t stream) {

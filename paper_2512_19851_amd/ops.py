@@ -167,6 +167,12 @@ def set_pressure_band(band: int) -> None:
     _lib.call("sten_tune_pressure", int(band))
 
 
+def set_adjoint_levels(levels: int) -> None:
+    """Transposed steps per launch of the several-step adjoint kernel (1..8; 0: built-in). Results are
+    unchanged."""
+    _lib.call("sten_tune_adjoint_levels", int(levels))
+
+
 class HiLoGrid:
     """An encoded grid in a device byte buffer: FP32 hi plane + int16 q plane."""
 

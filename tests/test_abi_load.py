@@ -197,6 +197,9 @@ def test_cavity_pressure_rejects_before_any_hip_call(lib):
     assert f(A + 8, B, O, K, 8, 128, 128, 3, 0.2, 0.3, 0.1, 0, None) == -6  # unaligned
     assert lib.sten_tune_pressure(-1) == -1
     assert lib.sten_tune_pressure(0) == 0
+    assert lib.sten_tune_adjoint_levels(-1) == -1
+    assert lib.sten_tune_adjoint_levels(9) == -1
+    assert lib.sten_tune_adjoint_levels(0) == 0
 
 
 def test_expr_run_rejects_before_any_hip_call(lib):

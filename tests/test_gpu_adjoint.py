@@ -169,15 +169,17 @@ def test_grad_without_c(ag):
     assert np.all(np.abs(got - oracle.jacobi5_adjoint(w32, 4)) <= oracle.bound_adjoint_fp32(w32, 4))
 
 
-ADJ_SHAPES = [(3, 3), (4, 5), (17, 253), (40, 260), (33, 1030), (130, 301), (9, 1024), (261, 250)]
+ADJ_SHAPES = [(3, 3), (4, 5), (17, 253), (40, 260), (33, 1030), (130, 301), (9, 1024), (261, 250), (100, 1024),
+              (64, 772), (257, 516)]
 
 
 @pytest.mark.parametrize("shape", ADJ_SHAPES, ids=lambda s: f"{s[0]}x{s[1]}")
 def test_adjoint_exact_many_steps(ag, shape):
     """Small integers: every FP32 operation of up to 8 transposed steps is exact, so the result equals the
-    FP64 oracle bit for bit. Shapes cross the tiles (8 or 16 rows, 240-256 columns) and strips of both
-    kernels, with ragged last tiles and widths that are not a multiple of 4 (element-wise path); T = 7 and
-    8 take two launches of the several-step kernel."""
+    FP64 oracle bit for bit. Shapes cross the one-step kernel's tiles (2 rows, 256 columns) and the
+    several-step streaming kernel's strips and bands: widths below 256 or not a multiple of 4 (clamped,
+    element-wise strips), multiples of 4 from 256 up (grid-aligned first and last strips), and grids wide
+    and tall enough for unmasked interior strips and bands (100 x 1024, 64 x 772, 257 x 516)."""
     rng = np.random.default_rng(sum(shape))
     w = rng.integers(-8, 9, shape).astype(np.float64)
     g = to_dev(w.astype(np.float32))
@@ -216,3 +218,21 @@ def test_adjoint_long_chain_within_bound(ag):
     got = to_host(ag.adjoint(to_dev(w.astype(np.float32)), 25)).astype(np.float64)
     ref = oracle.jacobi5_adjoint(w, 25)
     assert np.all(np.abs(got - ref) <= oracle.bound_adjoint_fp32(w, 25))
+
+
+@pytest.mark.parametrize("levels", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_adjoint_levels_per_launch(ag, levels):
+    """Every setting of transposed steps per launch gives the oracle's bits (small integers, T = 8, so every
+    FP32 operation is exact), on clamped, grid-aligned and interior strips."""
+    from paper_2512_19851_amd import ops
+
+    ops.set_adjoint_levels(levels)
+    try:
+        for shape in [(40, 260), (100, 1024), (33, 1030), (70, 517)]:
+            rng = np.random.default_rng(levels * 131 + sum(shape))
+            w = rng.integers(-8, 9, shape).astype(np.float64)
+            say(f"adjoint levels={levels} {shape}")
+            got = to_host(ag.adjoint(to_dev(w.astype(np.float32)), 8)).astype(np.float64)
+            assert np.array_equal(got, oracle.jacobi5_adjoint(w, 8)), f"levels={levels} {shape}"
+    finally:
+        ops.set_adjoint_levels(0)
