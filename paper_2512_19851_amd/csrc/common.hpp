@@ -75,6 +75,20 @@ bool launch_stream_grids_f64(const GridView<double>* views, int n, double c, int
 // One sweep of each of n FP64 grids (sweep.hip), in launches of up to 32
 // grids. Every grid: H, W >= 3, 16-byte aligned, even ld; returns false, with
 // nothing launched, otherwise.
-bool launch_sweep_grids_f64(const GridView<double>* views, int n, double c, hipStream_t s);
+// Ghost cells of the four neighbours' output views that mirror a grid's first
+// and last interior rows and columns, so that one sweep also does the ghost
+// exchange of depth 1 (NULL where there is no neighbour). Neighbours share
+// column (north, south) or row (west, east) coordinates with the grid.
+struct GridMirror {
+    double* north = nullptr;  // the north neighbour's last view row
+    double* south = nullptr;  // the south neighbour's first view row
+    double* west = nullptr;   // the west neighbour's last view column (row stride ld_west)
+    double* east = nullptr;   // the east neighbour's first view column (row stride ld_east)
+    int64_t ld_west = 0, ld_east = 0;
+};
+// With mirrors (one per view), each sweep also stores grid k's edge rows and
+// columns into mirrors[k]'s ghost cells.
+bool launch_sweep_grids_f64(const GridView<double>* views, int n, double c, hipStream_t s,
+                            const GridMirror* mirrors = nullptr);
 
 }  // namespace sten

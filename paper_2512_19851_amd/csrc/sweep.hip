@@ -183,12 +183,87 @@ struct SweepGrid {
     int64_t ld;
     int H, W;
     uint32_t tiles_x, first;
+    // mirrors of the edge rows and columns (depth-1 exchange), NULL where none
+    double* mn;
+    double* ms;
+    double* mw;
+    double* me;
+    int64_t ldw, lde;
 };
 
 struct SweepGrids {
     SweepGrid g[kMaxSweepGrids];
     int n;
 };
+
+// One tile of a multi-grid sweep that also stores the grid's edge values into
+// its neighbours' ghost cells (the depth-1 exchange, GridMirror): the tile
+// loop of sweep_tile, with each computed row's values at the first and last
+// interior row and column stored a second time, straight from registers.
+template <int ROWS, bool FULL>
+__device__ __forceinline__ void sweep_tile_mirror(const double* __restrict__ src, double* __restrict__ dst, int n,
+                                                  int i0, int jb, int lane, const SweepGrid& gr, double c) {
+    constexpr int V = 2;
+    const int W = gr.W;
+    const int64_t ld = gr.ld;
+    double r[ROWS + 2][V];
+#pragma unroll
+    for (int k = 0; k < ROWS + 2; ++k) {
+        if (FULL) {
+            typedef typename Vec<double, V>::type VT;
+            VT x = *reinterpret_cast<const VT*>(src + (int64_t)k * ld + jb);
+#pragma unroll
+            for (int e = 0; e < V; ++e) r[k][e] = x[e];
+        } else if (k < n + 2) {
+            load_vec<double, V>(src + (int64_t)k * ld, jb, W, r[k]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e) r[k][e] = 0.0;
+        }
+    }
+    double el[ROWS], er[ROWS];
+#pragma unroll
+    for (int k = 0; k < ROWS; ++k) {
+        el[k] = 0.0;
+        er[k] = 0.0;
+        if (FULL || k < n) {
+            const double* row = src + (int64_t)(k + 1) * ld;
+            if (lane == 0 && jb > 0 && jb <= W) el[k] = row[jb - 1];
+            if (lane == kWave - 1 && jb + V < W) er[k] = row[jb + V];
+        }
+    }
+    // this thread's columns that are the first (west mirror) or last (east mirror) interior column
+    const bool col_w = gr.mw != nullptr && jb <= 1 && 1 < jb + V;
+    const bool col_e = gr.me != nullptr && jb <= W - 2 && W - 2 < jb + V;
+#pragma unroll
+    for (int k = 0; k < ROWS; ++k) {
+        if (FULL || k < n) {
+            double left0 = __shfl_up(r[k + 1][V - 1], 1);
+            double rightv = __shfl_down(r[k + 1][0], 1);
+            if (lane == 0) left0 = el[k];
+            if (lane == kWave - 1) rightv = er[k];
+            double o[V];
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const double west = (e == 0) ? left0 : r[k + 1][e > 0 ? e - 1 : 0];
+                const double east = (e == V - 1) ? rightv : r[k + 1][e < V - 1 ? e + 1 : 0];
+                double t = r[k][e] + r[k + 2][e];  // N + S
+                t = t + west;                      // + W
+                t = t + east;                      // + E
+                o[e] = c * t;
+            }
+            store_vec<double, V>(dst + (int64_t)k * ld, jb, W, o);
+            const int i = i0 + k;
+            if ((i == 1 && gr.mn != nullptr) || (i == gr.H - 2 && gr.ms != nullptr)) {  // uniform per row
+                double* to = (i == 1 && gr.mn != nullptr) ? gr.mn : gr.ms;
+                store_vec<double, V>(to, jb, W, o);
+                if (i == 1 && i == gr.H - 2 && gr.mn != nullptr && gr.ms != nullptr) store_vec<double, V>(gr.ms, jb, W, o);
+            }
+            if (col_w) gr.mw[(int64_t)i * gr.ldw] = o[1 - jb];
+            if (col_e) gr.me[(int64_t)i * gr.lde] = o[W - 2 - jb];
+        }
+    }
+}
 
 template <int ROWS>
 __global__ __launch_bounds__(kBlock) void sweep_grids_kernel(const SweepGrids grids, double c) {
@@ -207,10 +282,39 @@ __global__ __launch_bounds__(kBlock) void sweep_grids_kernel(const SweepGrids gr
     const int wave_end = (jb - lane * V) + kWave * V;
     const double* src = gr.in + (int64_t)(i0 - 1) * gr.ld;
     double* dst = gr.out + (int64_t)i0 * gr.ld;
-    if (n == ROWS && wave_end <= gr.W)
+    const bool full = n == ROWS && wave_end <= gr.W;
+    const bool mirror = gr.mn != nullptr || gr.ms != nullptr || gr.mw != nullptr || gr.me != nullptr;
+    if (mirror) {
+        if (full)
+            sweep_tile_mirror<ROWS, true>(src, dst, n, i0, jb, lane, gr, c);
+        else
+            sweep_tile_mirror<ROWS, false>(src, dst, n, i0, jb, lane, gr, c);
+    } else if (full) {
         sweep_tile<double, V, ROWS, true>(src, dst, n, jb, lane, gr.W, gr.ld, c);
-    else
+    } else {
         sweep_tile<double, V, ROWS, false>(src, dst, n, jb, lane, gr.W, gr.ld, c);
+    }
+    // The interior columns past the row's blocks (at most 2, see the launcher) go to the last thread of
+    // the row's last block: the same expression, element by element.
+    const int covered = (int)gr.tiles_x * kBlock * V;
+    if (tx == gr.tiles_x - 1 && threadIdx.x == kBlock - 1 && covered < gr.W - 1) {
+        for (int k = 0; k < n; ++k) {
+            const int i = i0 + k;
+            const double* up = src + (int64_t)k * gr.ld;
+            const double* mid = up + gr.ld;
+            const double* down = mid + gr.ld;
+            for (int j = covered; j < gr.W - 1; ++j) {
+                double t = up[j] + down[j];  // N + S
+                t = t + mid[j - 1];          // + W
+                t = t + mid[j + 1];          // + E
+                const double o = c * t;
+                dst[(int64_t)k * gr.ld + j] = o;
+                if (i == 1 && gr.mn != nullptr) gr.mn[j] = o;
+                if (i == gr.H - 2 && gr.ms != nullptr) gr.ms[j] = o;
+                if (j == gr.W - 2 && gr.me != nullptr) gr.me[(int64_t)i * gr.lde] = o;
+            }
+        }
+    }
 }
 
 // Copy the boundary ring of u0 into d1 and (when not NULL) d2. Needs H, W >= 2.
@@ -455,7 +559,8 @@ sten_status run_chain_f64(double* a, double* b, int64_t H, int64_t W, int64_t ld
 // One sweep of each of n grids (H, W >= 3; 16-byte aligned, even ld), in
 // launches of up to kMaxSweepGrids grids. Returns false, with nothing
 // launched, when a grid does not meet the alignment the vector path needs.
-bool launch_sweep_grids_f64(const GridView<double>* views, int n, double c, hipStream_t s) {
+bool launch_sweep_grids_f64(const GridView<double>* views, int n, double c, hipStream_t s,
+                            const GridMirror* mirrors) {
     constexpr int ROWS = 4;
     for (int k = 0; k < n; ++k)
         if ((((uintptr_t)views[k].in | (uintptr_t)views[k].out) % 16) != 0 || views[k].ld % 2 != 0) return false;
@@ -471,8 +576,21 @@ bool launch_sweep_grids_f64(const GridView<double>* views, int n, double c, hipS
             g.ld = v.ld;
             g.H = v.H;
             g.W = v.W;
+            // blocks of 512 columns; when the last block would hold at most 2 interior columns (tile
+            // views of 2^k + 1 to 2^k + 3 columns), it is dropped and the row's last thread computes them
             g.tiles_x = ceil_div(v.W, (int64_t)kBlock * 2);
+            const int64_t tail = (int64_t)(v.W - 1) - (int64_t)(g.tiles_x - 1) * kBlock * 2;
+            if (g.tiles_x > 1 && tail <= 2) --g.tiles_x;
             g.first = first;
+            if (mirrors != nullptr) {
+                const GridMirror& m = mirrors[k0 + k];
+                g.mn = m.north;
+                g.ms = m.south;
+                g.mw = m.west;
+                g.me = m.east;
+                g.ldw = m.ld_west;
+                g.lde = m.ld_east;
+            }
             first += g.tiles_x * ceil_div(v.H - 2, ROWS);
         }
         if (first > 0) sweep_grids_kernel<ROWS><<<first, kBlock, 0, s>>>(args, c);

@@ -382,33 +382,67 @@ sten_status exchange(sten_tiled_s* p, int k, hipStream_t compute, hipStream_t co
     return check_launch();
 }
 
+// The ghost cells of neighbour nb's view in buffer k at its view row `row` (north/south) or column
+// `col` (west/east), -1 selecting the last one.
+double* ghost_line(const sten_tiled_s* p, int nb, int k, int row, int col) {
+    const Tile& u = p->tiles[nb];
+    const View nv = tile_view(u, p->g);
+    const int r = row < 0 ? nv.vh - 1 : row, cc = col < 0 ? nv.vw - 1 : col;
+    return u.buf[k] + nv.off + (int64_t)r * u.ldt + cc;
+}
+
 // s sweeps of every tile from buffer src to buffer 1 - src: one sweep as one
 // launch of the single-sweep kernel over all tiles (per 32 tiles), several as
 // one launch of the streaming blocked kernel over all tiles (per 32 tiles).
-void sweep_tiles(sten_tiled_s* p, int src, int s, double c, hipStream_t compute) {
+// fuse (depth 1, one sweep): the sweep also stores every tile's edge rows and
+// columns into its neighbours' ghost cells in buffer 1 - src, which is then a
+// complete exchange. Returns whether it did.
+bool sweep_tiles(sten_tiled_s* p, int src, int s, double c, hipStream_t compute, bool fuse) {
     const int dst = 1 - src;
     std::vector<GridView<double>> views;
+    std::vector<GridMirror> mirrors;
+    // a tile whose view is under 3 x 3 has no interior point and is not swept, so it would not
+    // refresh its neighbours' ghost copies of its values in buffer dst: no fused exchange then
+    for (const Tile& t : p->tiles) {
+        const View v = tile_view(t, p->g);
+        if (v.vh < 3 || v.vw < 3) fuse = false;
+    }
     for (const Tile& t : p->tiles) {
         const View v = tile_view(t, p->g);
         if (v.vh < 3 || v.vw < 3) continue;
         views.push_back(GridView<double>{t.buf[src] + v.off, t.buf[dst] + v.off, v.vh, v.vw, t.ldt});
+        if (fuse) {
+            GridMirror m;
+            if (t.nb[0] >= 0) m.north = ghost_line(p, t.nb[0], dst, -1, 0);
+            if (t.nb[1] >= 0) m.south = ghost_line(p, t.nb[1], dst, 0, 0);
+            if (t.nb[2] >= 0) {
+                m.west = ghost_line(p, t.nb[2], dst, 0, -1);
+                m.ld_west = p->tiles[t.nb[2]].ldt;
+            }
+            if (t.nb[3] >= 0) {
+                m.east = ghost_line(p, t.nb[3], dst, 0, 0);
+                m.ld_east = p->tiles[t.nb[3]].ldt;
+            }
+            mirrors.push_back(m);
+        }
     }
-    if (views.empty()) return;
+    if (views.empty()) return false;
     const int64_t launches = ((int64_t)views.size() + kMaxStreamGridsPerLaunch - 1) / kMaxStreamGridsPerLaunch;
     if (s == 1) {
-        if (launch_sweep_grids_f64(views.data(), (int)views.size(), c, compute)) {
+        if (launch_sweep_grids_f64(views.data(), (int)views.size(), c, compute, fuse ? mirrors.data() : nullptr)) {
             p->n_sweep_launches += launches;
-            return;
+            return fuse;
         }
-        // a view off the 16-byte alignment the plan lays out: one launch per tile
+        // a view off the 16-byte alignment the plan lays out: one launch per tile, no fused exchange
         for (const GridView<double>& v : views) {
             launch_sweep_f64_internal(v.in, v.out, v.H, v.W, v.ld, c, compute);
             ++p->n_sweep_launches;
         }
-        return;
+        return false;
     }
     launch_stream_grids_f64(views.data(), (int)views.size(), c, s, compute);
     p->n_sweep_launches += launches;
+    return false;
 }
 
 sten_status make_plan(int64_t H, int64_t W, int pr, int pc, int g, int mode, sten_tiled_s* p, Layout& L) {
@@ -558,12 +592,23 @@ sten_status sten_tiled_run(sten_tiled_handle p, int32_t T, double c, hipStream_t
     // chunks of at most g sweeps between exchanges, split as evenly as the chunk count allows
     const int chunks = (T + p->g - 1) / p->g;
     const int base = T / chunks, extra = T % chunks;
+    bool fresh = false;  // the previous sweep did the exchange of the buffer it wrote
     for (int k = 0; k < chunks; ++k) {
         const int src = p->cur, dst = 1 - p->cur;
-        sten_status st = exchange(p, src, compute, comm);
-        if (st != STEN_OK) return st;
-        sweep_tiles(p, src, base + (k < extra ? 1 : 0), c, compute);
+        if (!fresh) {
+            sten_status st = exchange(p, src, compute, comm);
+            if (st != STEN_OK) return st;
+        }
+        // direct mode at depth 1 stores the edge values into the neighbours' ghosts within the sweep
+        // (as a peer store across GPUs would), except in the run's last sweep, whose ghosts the next
+        // exchange refreshes when they are read
+        const bool fuse = p->mode == 1 && p->g == 1 && k + 1 < chunks;
+        fresh = sweep_tiles(p, src, base + (k < extra ? 1 : 0), c, compute, fuse);
         ++p->local_epoch[dst];
+        if (fresh) {
+            p->ghost_epoch[dst] = p->local_epoch[dst];
+            ++p->n_exchanges;
+        }
         p->cur = dst;
     }
     return check_launch();

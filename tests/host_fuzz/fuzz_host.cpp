@@ -29,7 +29,8 @@ bool launch_stream_grids_f64(const GridView<double>*, int, double, int, hipStrea
     std::fprintf(stderr, "unexpected launch\n");
     std::abort();
 }
-bool launch_sweep_grids_f64(const GridView<double>*, int, double, hipStream_t) {
+struct GridMirror;
+bool launch_sweep_grids_f64(const GridView<double>*, int, double, hipStream_t, const GridMirror*) {
     std::fprintf(stderr, "unexpected launch\n");
     std::abort();
 }

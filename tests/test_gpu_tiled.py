@@ -210,3 +210,45 @@ def test_tiled_depth1_one_launch_per_sweep(ops, exchange):
         assert np.array_equal(to_host(t.gather()), oracle.jacobi5(u0, 5))
         st = t.stats()
         assert st["sweep_launches"] == 5 * launches
+
+
+def test_depth1_direct_exchange_in_the_sweep(ops):
+    """Direct mode at depth 1: every sweep but a run's last also stores the tiles' edge rows and columns into
+    their neighbours' ghost cells (the exchange done inside the sweep). Runs continue bit-exact across calls
+    and with a separate exchange in between, and the exchanges still number one per sweep; a tiling with
+    tiles too small to sweep (1-row tiles) falls back to separate exchanges."""
+    u0 = normal_grid(130, 517, seed=21)
+    t = ops.TiledGrid(130, 517, 3, 4, ghost=1, exchange="direct")
+    t.scatter(to_dev(u0))
+    say("tiled depth 1 direct fused: 4 + 3 sweeps, exchange, 2 sweeps")
+    t.run(4)
+    t.run(3)
+    assert np.array_equal(to_host(t.gather()), oracle.jacobi5(u0, 7))
+    st = t.stats()
+    assert st["exchanges"] == 7 and st["skipped"] == 0 and st["sweep_launches"] == 7
+    t.exchange()
+    t.run(2)
+    assert np.array_equal(to_host(t.gather()), oracle.jacobi5(u0, 9))
+    st = t.stats()  # the run's first exchange finds the ghosts fresh and is skipped
+    assert st["exchanges"] == 9 and st["skipped"] == 1
+    u1 = normal_grid(12, 40, seed=2)
+    t2 = ops.TiledGrid(12, 40, 12, 2, ghost=1, exchange="direct")
+    t2.scatter(to_dev(u1))
+    say("tiled depth 1 direct, 1-row tiles")
+    t2.run(6)
+    assert np.array_equal(to_host(t2.gather()), oracle.jacobi5(u1, 6))
+    assert t2.stats()["exchanges"] == 6
+
+
+@pytest.mark.parametrize("exchange", ["packed", "direct"])
+def test_depth1_views_past_whole_blocks(ops, exchange):
+    """Tile views 513, 514, 515 and 1026 columns wide: the one-sweep launch over all tiles covers 512 columns
+    per block and leaves the last 0 to 2 interior columns of a row to one thread; bit-exact for T = 1..4."""
+    for (H, W, pr, pc) in [(40, 1024, 1, 2), (40, 1026, 1, 2), (40, 1028, 1, 2), (30, 1536, 2, 3), (20, 4096, 2, 4)]:
+        u0 = normal_grid(H, W, seed=W + pr)
+        for T in (1, 2, 4):
+            say(f"tiled depth 1 {exchange} {H}x{W} {pr}x{pc} T={T}")
+            t = ops.TiledGrid(H, W, pr, pc, ghost=1, exchange=exchange)
+            t.scatter(to_dev(u0))
+            t.run(T)
+            assert np.array_equal(to_host(t.gather()), oracle.jacobi5(u0, T)), f"{H}x{W} {pr}x{pc} T={T}"
