@@ -28,9 +28,13 @@
 //    ring. A sweep of the view leaves the view's own ring unchanged, so after
 //    s <= g sweeps a point at distance d from a ghost side is exact when
 //    d >= s: every owned point is. Results are bit-identical to the
-//    single-grid method. Chunks of one sweep use the plain sweep kernel per
-//    tile; chunks of s > 1 sweeps use one launch of the streaming blocked
-//    kernel over all tile views.
+//    single-grid method. Chunks of one sweep use one launch of the one-sweep
+//    kernel over all tile views, chunks of s > 1 sweeps one launch of the
+//    streaming blocked kernel over all tile views.
+//  * Direct mode at depth 1 does the exchange inside the sweep: the sweep also
+//    stores each tile's first and last interior rows and columns into its
+//    neighbours' ghost cells of the buffer it writes (except in a run's last
+//    sweep), so one launch per sweep remains.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
