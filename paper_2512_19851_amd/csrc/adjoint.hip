@@ -207,6 +207,136 @@ __global__ __launch_bounds__(kAdjTileBlock) void adjoint_tile_kernel(const float
     }
 }
 
+// The transposed step at one point (r, j) read straight from g (zeros outside
+// the grid): the value a wave's edge lane needs one column past its tile.
+__device__ __forceinline__ float adj_point_at(const float* __restrict__ g, int r, int j, int H, int W, int64_t ld,
+                                              float c) {
+    auto at = [&](int rr, int jj) -> float {
+        return (rr >= 0 && rr < H && jj >= 0 && jj < W) ? g[(int64_t)rr * ld + jj] : 0.0f;
+    };
+    return adj_point(at(r - 1, j), at(r + 1, j), at(r, j - 1), at(r, j + 1), at(r, j), adj_interior_row(r - 1, H),
+                     adj_interior_row(r + 1, H), adj_interior_row(r, H), adj_col(j, W), c);
+}
+
+// The dL/dc term of one tile row: sum over the row's interior points m of g[m] * nbrsum(u)[m], the
+// neighbour sum in FP32 in the order N, S, W, E, product and sum in FP64, elements in order.
+template <bool VEC>
+__device__ __forceinline__ void adj_dot_row(double& acc, const float (&gm)[kAdjV], const float (&un)[kAdjV],
+                                            const float (&um)[kAdjV], const float (&us)[kAdjV],
+                                            const float* __restrict__ urow, int j0, bool edge_w, bool edge_e,
+                                            const AdjCol (&col)[kAdjV]) {
+    float ul = stream::lane_from_lower(um[kAdjV - 1]);
+    float ur = stream::lane_from_upper(um[0]);
+    if (edge_w) ul = urow[j0 - 1];
+    if (edge_e) ur = urow[j0 + kAdjV];
+#pragma unroll
+    for (int e = 0; e < kAdjV; ++e) {
+        if (col[e].in) {
+            const float uw = e == 0 ? ul : um[e > 0 ? e - 1 : 0];
+            const float ue = e == kAdjV - 1 ? ur : um[e < kAdjV - 1 ? e + 1 : 0];
+            float ns = un[e] + us[e];
+            ns = ns + uw;
+            ns = ns + ue;
+            acc += (double)gm[e] * (double)ns;
+        }
+    }
+}
+
+// Two transposed steps with their dL/dc terms in one launch, on the tiles of
+// the one-step kernel (2 rows by 256 columns per one-wave workgroup):
+// lambda_k = S^T lambda_{k+1} on the tile's rows and one row either side
+// (from 6 loaded rows of lambda_{k+1}; the wave's edge lanes compute the one
+// column past the tile from g directly), then lambda_{k-1} = S^T lambda_k on
+// the tile's rows. Every value is the one-step kernel's, and each step's sum is
+// reduced over the workgroup and added to the partial sum in the order two
+// one-step launches would add them, so the results are bit-identical to two
+// launches of the one-step kernel.
+template <bool VEC>
+__global__ __launch_bounds__(kAdjTileBlock) void adjoint_tile2_kernel(
+    const float* __restrict__ g, const float* __restrict__ u1, const float* __restrict__ u2,
+    float* __restrict__ out, double* __restrict__ partials, int accumulate, int H, int W, int64_t ld, float c,
+    uint32_t tiles_x) {
+    constexpr int R = kAdjRows;  // 2
+    const uint32_t tile = xcd_tile_of_block(blockIdx.x, gridDim.x);
+    const uint32_t ty = tile / tiles_x;
+    const uint32_t tx = tile - ty * tiles_x;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int j0 = ((int)tx * kAdjTileBlock + (int)threadIdx.x) * kAdjV;
+    const int i0 = (int)ty * R;
+    const bool edge_w = lane == 0 && j0 > 0 && j0 <= W;
+    const bool edge_e = lane == kWave - 1 && j0 + kAdjV < W;
+    AdjCol col[kAdjV];
+#pragma unroll
+    for (int e = 0; e < kAdjV; ++e) col[e] = adj_col(j0 + e, W);
+
+    float a[R + 4][kAdjV];   // lambda_{k+1}, rows i0-2 .. i0+R+1
+    float q1[R + 2][kAdjV];  // u_k, rows i0-1 .. i0+R
+    float q2[R + 2][kAdjV];  // u_{k-1}, rows i0-1 .. i0+R
+#pragma unroll
+    for (int m = 0; m < R + 4; ++m) adj_load<VEC>(g, i0 - 2 + m, H, W, ld, j0, a[m]);
+#pragma unroll
+    for (int m = 0; m < R + 2; ++m) {
+        adj_load<VEC>(u1, i0 - 1 + m, H, W, ld, j0, q1[m]);
+        adj_load<VEC>(u2, i0 - 1 + m, H, W, ld, j0, q2[m]);
+    }
+
+    // step 1: lambda_k on rows i0-1 .. i0+R (zeros outside the grid, as a one-step launch's loads give)
+    float b[R + 2][kAdjV];
+    double acc1 = 0.0;
+#pragma unroll
+    for (int m = 0; m < R + 2; ++m) {
+        const int r = i0 - 1 + m;
+        if (r < 0 || r >= H) {
+#pragma unroll
+            for (int e = 0; e < kAdjV; ++e) b[m][e] = 0.0f;
+            continue;
+        }
+        const float* grow = g + (int64_t)r * ld;
+        float lft = stream::lane_from_lower(a[m + 1][kAdjV - 1]);
+        float rgt = stream::lane_from_upper(a[m + 1][0]);
+        if (edge_w) lft = grow[j0 - 1];
+        if (edge_e) rgt = grow[j0 + kAdjV];
+        const bool rn = adj_interior_row(r - 1, H), rs = adj_interior_row(r + 1, H), rin = adj_interior_row(r, H);
+#pragma unroll
+        for (int e = 0; e < kAdjV; ++e) {
+            const float w = e == 0 ? lft : a[m + 1][e > 0 ? e - 1 : 0];
+            const float ea = e == kAdjV - 1 ? rgt : a[m + 1][e < kAdjV - 1 ? e + 1 : 0];
+            b[m][e] = adj_point(a[m][e], a[m + 2][e], w, ea, a[m + 1][e], rn, rs, rin, col[e], c);
+        }
+        // the tile's own rows: the step's dL/dc term, as the one-step kernel sums it
+        if (m >= 1 && m <= R && rin)
+            adj_dot_row<VEC>(acc1, a[m + 1], q1[m - 1], q1[m], q1[m + 1], u1 + (int64_t)r * ld, j0, edge_w, edge_e,
+                             col);
+    }
+    // step 2: lambda_{k-1} on the tile's rows; the edge lanes' neighbour column of lambda_k from g
+    double acc2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int r = i0 + k;
+        if (r >= H) continue;  // uniform over the workgroup
+        float lft = stream::lane_from_lower(b[k + 1][kAdjV - 1]);
+        float rgt = stream::lane_from_upper(b[k + 1][0]);
+        if (edge_w) lft = adj_point_at(g, r, j0 - 1, H, W, ld, c);
+        if (edge_e) rgt = adj_point_at(g, r, j0 + kAdjV, H, W, ld, c);
+        const bool rn = adj_interior_row(r - 1, H), rs = adj_interior_row(r + 1, H), rin = adj_interior_row(r, H);
+        float o[kAdjV];
+#pragma unroll
+        for (int e = 0; e < kAdjV; ++e) {
+            const float w = e == 0 ? lft : b[k + 1][e > 0 ? e - 1 : 0];
+            const float ea = e == kAdjV - 1 ? rgt : b[k + 1][e < kAdjV - 1 ? e + 1 : 0];
+            o[e] = adj_point(b[k][e], b[k + 2][e], w, ea, b[k + 1][e], rn, rs, rin, col[e], c);
+        }
+        adj_store<VEC>(out, r, ld, j0, 0, W, o);
+        if (rin) adj_dot_row<VEC>(acc2, b[k + 1], q2[k], q2[k + 1], q2[k + 2], u2 + (int64_t)r * ld, j0, edge_w, edge_e, col);
+    }
+    const double t1 = block_sum<kAdjTileBlock>(acc1);
+    const double t2 = block_sum<kAdjTileBlock>(acc2);
+    if (threadIdx.x == 0) {
+        const double p1 = accumulate ? partials[blockIdx.x] + t1 : t1;
+        partials[blockIdx.x] = p1 + t2;
+    }
+}
+
 // Several transposed steps per launch (no dL/dc): the streaming form of
 // temporal blocking, as in the forward kernel. One wave owns a strip of 256
 // loaded columns (4 floats per lane) and a band of output rows, and walks the
@@ -503,6 +633,13 @@ int adj_resident_waves(const void* kernel) {
     return cus * per_cu;
 }
 
+template <bool VEC>
+void launch_adjoint_step2(const float* g, const float* u1, const float* u2, float* out, double* partials,
+                          int accumulate, int H, int W, int64_t ld, float c, hipStream_t s) {
+    adjoint_tile2_kernel<VEC><<<adj_blocks(H, W), kAdjTileBlock, 0, s>>>(g, u1, u2, out, partials, accumulate, H, W,
+                                                                         ld, c, adj_tiles_x(W));
+}
+
 template <int TL>
 void launch_adjoint_stream_levels(const float* g, float* out, int H, int W, int64_t ld, float c, bool vec,
                                   hipStream_t s) {
@@ -579,15 +716,28 @@ sten_status adjoint_seg(const float* lam_in, const float* states, int32_t nsteps
                         (states != nullptr ? (uintptr_t)states : 0)) % 16) == 0) && ld % kAdjV == 0;
     const float* src = lam_in;
     if (states != nullptr && partials != nullptr) {
-        // one fused launch per step: lambda_k from lambda_{k+1}, plus the step's dL/dc term
-        for (int32_t s = 1; s <= nsteps; ++s) {
-            float* dst = ((nsteps - s) % 2 == 0) ? lam_out : work;
+        // fused launches of two steps (the last one alone when nsteps is odd): lambda from lambda, plus
+        // each step's dL/dc term; the last launch writes lam_out
+        const int launches = (nsteps + 1) / 2;
+        int32_t s = 1;  // the next step: lambda_{k1 - s} from lambda_{k1 - s + 1}, with state u_{k1 - s}
+        for (int l = 1; l <= launches; ++l) {
+            float* dst = ((launches - l) % 2 == 0) ? lam_out : work;
             const float* u = states + (int64_t)(nsteps - s) * pstride;
             const int acc = (s == 1 && reset) ? 0 : 1;
-            if (vec)
-                launch_adjoint_step<true>(src, u, dst, partials, acc, h, w, ld, c, stream);
-            else
-                launch_adjoint_step<false>(src, u, dst, partials, acc, h, w, ld, c, stream);
+            if (s + 1 <= nsteps) {
+                const float* u_next = states + (int64_t)(nsteps - s - 1) * pstride;
+                if (vec)
+                    launch_adjoint_step2<true>(src, u, u_next, dst, partials, acc, h, w, ld, c, stream);
+                else
+                    launch_adjoint_step2<false>(src, u, u_next, dst, partials, acc, h, w, ld, c, stream);
+                s += 2;
+            } else {
+                if (vec)
+                    launch_adjoint_step<true>(src, u, dst, partials, acc, h, w, ld, c, stream);
+                else
+                    launch_adjoint_step<false>(src, u, dst, partials, acc, h, w, ld, c, stream);
+                s += 1;
+            }
             src = dst;
         }
         return check_launch();
