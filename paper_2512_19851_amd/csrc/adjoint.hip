@@ -8,11 +8,12 @@
 // for EVERY point n (ring included). T transposed sweeps applied to
 // w = dL/du_T give dL/du0. The derivative with respect to c is
 //     dL/dc = sum_k sum_{interior m} lambda_{k+1}[m] * nbrsum(u_k)[m],
-// lambda_k = dL/du_k, which needs the forward states u_k: one fused kernel per
-// transposed step produces lambda_k from lambda_{k+1} and adds that step's
-// dot product, accumulated in FP64, into per-workgroup partial sums (each
-// workgroup owns a fixed tile, so the sum is deterministic); a single-block
-// kernel reduces the partials in a fixed order.
+// lambda_k = dL/du_k, which needs the forward states u_k: fused kernels of one
+// or two transposed steps produce lambda_k from lambda_{k+1} and add each
+// step's dot product, accumulated in FP64, into per-workgroup partial sums
+// (each workgroup owns a fixed tile, so the sum is deterministic); a
+// single-block kernel reduces the partials in a fixed order. Without dL/dc,
+// a streaming kernel applies several transposed steps per launch.
 //
 // FP32 arithmetic, neighbour terms in the order N, S, W, E (missing or ring
 // neighbours contribute an exact zero), then one multiplication by c and, on
