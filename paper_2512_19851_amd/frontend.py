@@ -64,6 +64,8 @@ class InPlaceDependencyError(ValueError):
 # ---------------------------------------------------------------------------
 
 class Expr:
+    __slots__ = ()
+
     def __add__(self, o):
         return BinOp("+", self, _wrap(o))
 
@@ -101,25 +103,25 @@ class Expr:
         raise NotImplementedError("only ** 2 is supported")
 
 
-@dataclass(eq=False)
+@dataclass(eq=False, slots=True)
 class Const(Expr):
     value: float
 
 
-@dataclass(eq=False)
+@dataclass(eq=False, slots=True)
 class Ref(Expr):
     array: "Array"
     region: tuple  # (r0, r1, c0, c1), half-open, step 1
 
 
-@dataclass(eq=False)
+@dataclass(eq=False, slots=True)
 class BinOp(Expr):
     op: str
     a: Expr
     b: Expr
 
 
-@dataclass(eq=False)
+@dataclass(eq=False, slots=True)
 class Unary(Expr):
     op: str  # "neg" or "sq"
     a: Expr
@@ -147,16 +149,27 @@ def _norm(s, n: int) -> tuple[int, int]:
     raise TypeError("indices must be ints or slices")
 
 
+_REGION_TEXT: dict = {}
+
+
 def _walk(e: Expr, names: dict, refs: list) -> str:
     """One pass over an expression: collects its slice references in order and returns the
     parameterised AST text (arrays become placeholders A0, A1, ... in order of first use)."""
-    if isinstance(e, Ref):
+    t = type(e)
+    if t is Ref:
         refs.append(e)
-        k = names.setdefault(e.array.uid, f"A{len(names)}")
-        return f"{k}[{e.region}]"
-    if isinstance(e, BinOp):
+        k = names.get(e.array.uid)
+        if k is None:
+            k = names[e.array.uid] = f"A{len(names)}"
+        rt = _REGION_TEXT.get(e.region)
+        if rt is None:
+            if len(_REGION_TEXT) > 65536:
+                _REGION_TEXT.clear()
+            rt = _REGION_TEXT[e.region] = f"[{e.region}]"
+        return k + rt
+    if t is BinOp:
         return f"({_walk(e.a, names, refs)}{e.op}{_walk(e.b, names, refs)})"
-    if isinstance(e, Const):
+    if t is Const:
         return repr(e.value)
     return f"{e.op}({_walk(e.a, names, refs)})"
 
@@ -179,6 +192,19 @@ def _ring_parts(H: int, W: int) -> tuple:
             (0, 1, 1, W - 1), (H - 1, H, 1, W - 1), (1, H - 1, 0, 1), (1, H - 1, W - 1, W))
 
 
+_REGION_CACHES: dict = {}
+
+
+def _region_cache(shape: tuple) -> dict:
+    """Normalised slice pairs of arrays of one shape (shared by every array of that shape)."""
+    c = _REGION_CACHES.get(shape)
+    if c is None:
+        if len(_REGION_CACHES) > 256:
+            _REGION_CACHES.clear()
+        c = _REGION_CACHES[shape] = {}
+    return c
+
+
 class Array:
     """A lazily computed FP64 grid owned by a Context."""
 
@@ -189,12 +215,23 @@ class Array:
         self.data = ctx.backend.alloc(self.shape)  # zeros
         H, W = self.shape
         self.ring = (_ZERO_BITS,) * 8 if H >= 3 and W >= 3 else None
+        self._regions = _region_cache(self.shape)
 
     def _region(self, key) -> tuple:
         if not isinstance(key, tuple) or len(key) != 2:
             raise IndexError("two indices or slices are required")
-        r0, r1 = _norm(key[0], self.shape[0])
-        c0, c1 = _norm(key[1], self.shape[1])
+        a, b = key
+        if type(a) is slice and type(b) is slice:
+            # programs repeat the same few slices: remember their normalised form per array shape
+            ck = (a.start, a.stop, a.step, b.start, b.stop, b.step)
+            reg = self._regions.get(ck)
+            if reg is None:
+                reg = _norm(a, self.shape[0]) + _norm(b, self.shape[1])
+                if len(self._regions) < 4096:
+                    self._regions[ck] = reg
+            return reg
+        r0, r1 = _norm(a, self.shape[0])
+        c0, c1 = _norm(b, self.shape[1])
         return (r0, r1, c0, c1)
 
     def __getitem__(self, key) -> Ref:
