@@ -809,7 +809,7 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extensions", action="store_true")
     ap.add_argument("--mode", choices=["step", "sweep", "copy", "hilo", "tb", "cavity", "pressure", "batch", "adjoint",
-                                       "tiled", "mixed"],
+                                       "tiled", "mixed", "frontend"],
                     default="step",
                     help="step: the benchmark; sweep: only --kernel-reps sweep launches; "
                          "copy: only --kernel-reps plain grid copies (counter calibration); "
@@ -820,7 +820,8 @@ def main() -> int:
                          "batch: only the batched extension (--sweeps, --steps graph replays); "
                          "adjoint: only the gradient extension (1024^2, T = 10); "
                          "tiled: only the tiled extension (--n, --sweeps); "
-                         "mixed: only the hi/lo extension (--n, --sweeps; timed against one sweep per launch)")
+                         "mixed: only the hi/lo extension (--n, --sweeps; timed against one sweep per launch); "
+                         "frontend: only the lazy-frontend pipelining runs (4096^2 and 16384^2)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -850,6 +851,9 @@ def main() -> int:
         return 0
     if args.mode == "adjoint":
         print(json.dumps({"mode": "adjoint", **bench_adjoint(10, args)}), flush=True)
+        return 0
+    if args.mode == "frontend":
+        print(json.dumps({"mode": "frontend", **bench_frontend(ops, args)}), flush=True)
         return 0
     if args.mode in ("tiled", "mixed"):
         n, T = args.n, args.sweeps

@@ -146,6 +146,16 @@ sten_status sten_sweep_f32(const float* src, float* dst, int64_t H, int64_t W, i
 sten_status sten_sweep_chain_f64(double* a, double* b, int64_t H, int64_t W, int64_t ld, int32_t m, double c,
                                  hipStream_t stream);
 
+/* The same m sweeps when iterate m-1 is not needed afterwards (the lazy
+ * frontend uses it when the next recorded node overwrites the other array's
+ * whole interior, Section III-B): iterate m lands in the array sweep m writes
+ * (b for odd m, a for even m), with the same bits as sten_sweep_chain_f64;
+ * the other array's interior is left unspecified and its ring untouched. All
+ * m sweeps run as blocked launches, so the chain costs no extra single-sweep
+ * pass. Arguments, checks and status codes as sten_sweep_chain_f64. */
+sten_status sten_sweep_chain_last_f64(double* a, double* b, int64_t H, int64_t W, int64_t ld, int32_t m, double c,
+                                      hipStream_t stream);
+
 /*
  * Temporal blocking (the same method, a different schedule): each launch
  * applies up to `levels` sweeps while reading and writing the grid once, so one

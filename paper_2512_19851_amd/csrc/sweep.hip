@@ -514,7 +514,9 @@ void launch_sweep_f64_internal(const double* in, double* out, int H, int W, int6
 // m sweeps ping-ponging between a and b from a (the listing's loop on two
 // arrays with equal rings): the first m-1 as blocked launches that end in the
 // array iterate m-1 belongs to, then one plain sweep into the other array.
-sten_status run_chain_f64(double* a, double* b, int64_t H, int64_t W, int64_t ld, int32_t m, double c,
+// keep_prev: the other array ends holding iterate m-1 (else its interior is left unspecified, and all m
+// sweeps run blocked)
+sten_status run_chain_f64(double* a, double* b, int64_t H, int64_t W, int64_t ld, int32_t m, double c, bool keep_prev,
                           hipStream_t stream) {
     if (H < 0 || W < 0 || (H > 0 && ld < W) || m < 0 || H > INT32_MAX / 2 || W > INT32_MAX / 2)
         return STEN_ERR_ARG;
@@ -528,7 +530,7 @@ sten_status run_chain_f64(double* a, double* b, int64_t H, int64_t W, int64_t ld
     const int L = sched == 0 ? default_levels<double>(H, W) : sched;
     const bool blocked = L > 1 && (((uintptr_t)a | (uintptr_t)b) % 16) == 0 && ld % 2 == 0 &&
                          W * (int64_t)sizeof(double) < ((int64_t)1 << 30);
-    const int n = m - 1;  // sweeps before the last one
+    const int n = keep_prev ? m - 1 : m;  // sweeps before the last single one (all of them without keep_prev)
     const double* src = a;
     if (blocked && n >= 2) {
         // k launches; launch j writes b for odd j, a for even j, and the k-th must write the array
@@ -552,7 +554,7 @@ sten_status run_chain_f64(double* a, double* b, int64_t H, int64_t W, int64_t ld
             src = dst;
         }
     }
-    launch_sweep_f64_internal(src, src == a ? b : a, h, w, ld, c, stream);
+    if (keep_prev) launch_sweep_f64_internal(src, src == a ? b : a, h, w, ld, c, stream);
     return check_launch();
 }
 
@@ -640,7 +642,12 @@ sten_status sten_fill_rect_f64(double* grid, int64_t H, int64_t W, int64_t ld, i
 
 sten_status sten_sweep_chain_f64(double* a, double* b, int64_t H, int64_t W, int64_t ld, int32_t m, double c,
                                  hipStream_t stream) {
-    return sten::run_chain_f64(a, b, H, W, ld, m, c, stream);
+    return sten::run_chain_f64(a, b, H, W, ld, m, c, true, stream);
+}
+
+sten_status sten_sweep_chain_last_f64(double* a, double* b, int64_t H, int64_t W, int64_t ld, int32_t m, double c,
+                                      hipStream_t stream) {
+    return sten::run_chain_f64(a, b, H, W, ld, m, c, false, stream);
 }
 
 sten_status sten_sweep_f64(const double* src, double* dst, int64_t H, int64_t W, int64_t ld, double c,

@@ -248,7 +248,7 @@ class Array:
         return self.data
 
 
-@dataclass
+@dataclass(slots=True)
 class Node:
     out: Array
     region: tuple
@@ -271,7 +271,8 @@ class Context:
         self.backend = backend if backend is not None else GpuBackend()
         self.nodes: list[Node] = []
         self.asts: dict[str, int] = {}
-        self.stats = {"nodes": 0, "flushes": 0, "launch_groups": 0, "fused_nodes": 0, "chained_nodes": 0}
+        self.stats = {"nodes": 0, "flushes": 0, "launch_groups": 0, "fused_nodes": 0, "chained_nodes": 0,
+                      "chains_last_only": 0}
         # per array (uid), in the current DAG: the last node that wrote it, and the nodes that read it
         # since. Earlier writers and readers are reached through these (a later write of an array depends
         # on its earlier writers and readers), so depths and the fusion test (within runs of consecutive
@@ -317,7 +318,7 @@ class Context:
             node.deps.add(self._writers[out.uid])
         node.depth = 1 + max((self.nodes[k].depth for k in node.deps), default=0)
         if node.depth > self.max_depth:
-            self.flush()
+            self.flush(pending=node)
             node.deps = set()
             node.depth = 1
         k = len(self.nodes)
@@ -339,6 +340,9 @@ class Context:
             return
         r0, r1, c0, c1 = region
         if r0 >= r1 or c0 >= c1:
+            return
+        H, W = out.shape
+        if r0 >= 1 and c0 >= 1 and r1 <= H - 1 and c1 <= W - 1:  # inside the interior: no ring part
             return
         value = struct.pack("<d", float(expr.value)) if isinstance(expr, Const) else None
         ring = list(out.ring)
@@ -393,8 +397,11 @@ class Context:
             groups.append([k])
         return groups
 
-    def flush(self) -> None:
-        """Send the current DAG to the backend (program order is a topological order)."""
+    def flush(self, pending: Node | None = None) -> None:
+        """Send the current DAG to the backend (program order is a topological order). `pending` is the
+        node whose recording caused the flush (it runs in the next DAG): when it overwrites the whole
+        interior of the array a final Jacobi chain leaves iterate m-1 in, that iterate is dead and the
+        chain need not produce it."""
         if not self.nodes:
             return
         groups = self._groups()
@@ -402,7 +409,17 @@ class Context:
         while i < len(groups):
             chain = self._chain_at(groups, i) if hasattr(self.backend, "run_chain") else []
             if chain:
-                self.backend.run_chain([self.nodes[k] for k in chain])
+                nodes = [self.nodes[k] for k in chain]
+                last = nodes[-1]
+                prev = match_jacobi(last)[0]  # the array holding iterate m-1 afterwards
+                H, W = prev.shape
+                dead = pending is not None and i + len(chain) == len(groups) and pending.out is prev and \
+                    pending.region == (1, H - 1, 1, W - 1)
+                if dead:
+                    self.backend.run_chain(nodes, keep_previous=False)
+                    self.stats["chains_last_only"] += 1
+                else:
+                    self.backend.run_chain(nodes)
                 self.stats["launch_groups"] += 1
                 self.stats["chained_nodes"] += len(chain)
                 i += len(chain)
@@ -643,8 +660,9 @@ class GpuBackend:
             self.ops.expr_run(text, [(a.data, r0, c0) for a, r0, c0 in ins],
                               [(a.data, r0, c0) for a, r0, c0 in outs], rows, cols)
 
-    def run_chain(self, chain: list) -> None:
-        """Jacobi nodes ping-ponging between two arrays with equal rings: one libsten chain call."""
+    def run_chain(self, chain: list, keep_previous: bool = True) -> None:
+        """Jacobi nodes ping-ponging between two arrays with equal rings: one libsten chain call. Without
+        keep_previous only the last iterate is produced (the other array's interior is left unspecified)."""
         from . import _lib
         from .ops import _ld, _stream_ptr
 
@@ -655,8 +673,8 @@ class GpuBackend:
             for n in chain:
                 self.run([n])
             return
-        _lib.call("sten_sweep_chain_f64", a.data.data_ptr(), b.data.data_ptr(), H, W, _ld(a.data), len(chain),
-                  float(c), _stream_ptr())
+        fn = "sten_sweep_chain_f64" if keep_previous else "sten_sweep_chain_last_f64"
+        _lib.call(fn, a.data.data_ptr(), b.data.data_ptr(), H, W, _ld(a.data), len(chain), float(c), _stream_ptr())
 
     def synchronize(self) -> None:
         self.torch.cuda.synchronize()

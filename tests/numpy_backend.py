@@ -48,16 +48,18 @@ class NumpyBackend:
             r0, r1, c0, c1 = n.region
             n.out.data[r0:r1, c0:c1] = v
 
-    def run_chain(self, chain):
+    def run_chain(self, chain, keep_previous=True):
         """A model of the library's chain plan on the CPU: the first m-1 sweeps as k blocked passes (each pass
         is `lev` sweeps of the oracle from the pass's source, that array's ring at every level), k chosen with
-        the parity that ends in the array of iterate m-1, then one plain sweep."""
+        the parity that ends in the array of iterate m-1, then one plain sweep. Without keep_previous all m
+        sweeps run as blocked passes and the other array's interior is then poisoned with NaN, so that a
+        result that depended on it would show."""
         a, c = fe.match_jacobi(chain[0])
         b = chain[0].out
         m = len(chain)
-        self.chains.append(m)
+        self.chains.append(m if keep_previous else -m)
         L = self.chain_levels
-        n = m - 1
+        n = m - 1 if keep_previous else m
         src = a
         if L > 1 and n >= 2:
             k = -(-n // L)
@@ -74,8 +76,11 @@ class NumpyBackend:
                 dst = b if j % 2 else a
                 dst.data[1:-1, 1:-1] = oracle.jacobi5(src.data, 1, c)[1:-1, 1:-1]
                 src = dst
-        dst = b if src is a else a
-        dst.data[1:-1, 1:-1] = oracle.jacobi5(src.data, 1, c)[1:-1, 1:-1]
+        other = b if src is a else a
+        if keep_previous:
+            other.data[1:-1, 1:-1] = oracle.jacobi5(src.data, 1, c)[1:-1, 1:-1]
+        else:
+            other.data[1:-1, 1:-1] = np.nan
 
     def synchronize(self):
         pass

@@ -194,6 +194,64 @@ def test_listing_chains_keep_both_arrays(levels, depth):
             assert ctx.stats["chained_nodes"] == T and be.chains == [T]
 
 
+def test_listing_chain_skips_dead_iterate():
+    """A chain flushed because the next Jacobi node needs a new DAG leaves iterate m-1 behind only to have
+    that node overwrite it: the chain then produces iterate m alone (the model poisons the other array),
+    and the final state still equals one node at a time."""
+    for depth, T in ((2, 9), (7, 25), (10, 200)):
+        be = NumpyBackend(chain_levels=10)
+        ctx = fe.Context(max_depth=depth, backend=be)
+        u1, u2 = listing_pair(ctx, 9, 12, T)
+        w1, w2 = numpy_listing_pair(9, 12, T)
+        assert np.array_equal(u1.data, w1) and np.array_equal(u2.data, w2), (depth, T)
+        assert ctx.stats["chains_last_only"] > 0 and any(m < 0 for m in be.chains)
+
+
+def _jac(dst, src):
+    dst[1:-1, 1:-1] = 0.25 * (src[:-2, 1:-1] + src[2:, 1:-1] + src[1:-1, :-2] + src[1:-1, 2:])
+
+
+def test_chain_keeps_iterate_that_is_read_or_partly_overwritten():
+    """The dead-iterate shortcut needs both: the chain is the flush's last launch group, and the node that
+    caused the flush overwrites the whole interior of the array holding iterate m-1."""
+    rng = np.random.default_rng(3)
+    init = rng.standard_normal((7, 9))
+    init[0, :] = init[-1, :] = init[:, 0] = init[:, -1] = 1.0
+    for case in ("partial", "read_after"):
+        be = NumpyBackend(chain_levels=3)
+        ctx = fe.Context(max_depth=3, backend=be)  # the node after the chain starts a new DAG
+        a, b, d = (ctx.create_array((7, 9)) for _ in range(3))
+        for u in (a, b):
+            u[0, :] = u[-1, :] = u[:, 0] = u[:, -1] = 1.0
+            u[1:-1, 1:-1] = 0.0
+        ref_a, ref_b, ref_d = np.zeros((7, 9)), np.zeros((7, 9)), np.zeros((7, 9))
+        for r in (ref_a, ref_b):
+            r[0, :] = r[-1, :] = r[:, 0] = r[:, -1] = 1.0
+        ctx.sync()
+        a.data[1:-1, 1:-1] = init[1:-1, 1:-1]
+        ref_a[1:-1, 1:-1] = init[1:-1, 1:-1]
+        src, dst, rs, rd = a, b, ref_a, ref_b
+        for _ in range(3):  # a chain of 3: iterate 3 in b, iterate 2 in a
+            dst[1:-1, 1:-1] = 0.25 * (src[:-2, 1:-1] + src[2:, 1:-1] + src[1:-1, :-2] + src[1:-1, 2:])
+            _jac(rd, rs)
+            src, dst, rs, rd = dst, src, rd, rs
+        if case == "partial":
+            a[1:3, 1:-1] = b[1:3, 1:-1] * 2.0  # overwrites only part of iterate 2, and causes the flush
+            ref_a[1:3, 1:-1] = ref_b[1:3, 1:-1] * 2.0
+            for _ in range(3):
+                a[1:3, 1:-1] = b[1:3, 1:-1] * 2.0
+        else:
+            d[1:-1, 1:-1] = a[1:-1, 1:-1] * 2.0  # reads iterate 2 after the chain, in the same DAG; the
+            # next node overwrites iterate 2 whole and causes the flush
+            ref_d[1:-1, 1:-1] = ref_a[1:-1, 1:-1] * 2.0
+            a[1:-1, 1:-1] = 0.25 * (b[:-2, 1:-1] + b[2:, 1:-1] + b[1:-1, :-2] + b[1:-1, 2:])
+            _jac(ref_a, ref_b)
+        ctx.sync()
+        for got, want in ((a, ref_a), (b, ref_b), (d, ref_d)):
+            assert np.array_equal(got.data, want), case
+        assert be.chains and all(m > 0 for m in be.chains), (case, be.chains)
+
+
 def test_no_chain_when_rings_differ():
     be = NumpyBackend()
     ctx = fe.Context(max_depth=1000, backend=be)

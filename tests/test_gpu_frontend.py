@@ -153,3 +153,39 @@ def test_sweep_chain_abi(schedule):
                 assert np.array_equal(to_host(other), states[m - 1]), (schedule, H, W, m)
     finally:
         ops.set_schedule(0)
+
+
+@pytest.mark.parametrize("schedule", [0, 1, 2, 12])
+def test_sweep_chain_last_abi(schedule):
+    """sten_sweep_chain_last_f64: iterate m in the array sweep m writes, bit for bit, for every chain length
+    0..26 (all sweeps as blocked launches); both rings untouched; the other array's interior is free."""
+    import torch
+
+    device()
+    from paper_2512_19851_amd import _lib, ops
+
+    try:
+        ops.set_schedule(schedule)
+        for H, W in ((5, 7), (64, 66), (130, 257), (41, 512), (300, 1024)):
+            a0 = np.random.default_rng(H * W + schedule + 1).standard_normal((H, W))
+            b0 = np.random.default_rng(H + W + 1).standard_normal((H, W))
+            b0[0, :], b0[-1, :], b0[:, 0], b0[:, -1] = a0[0, :], a0[-1, :], a0[:, 0], a0[:, -1]
+            states = [a0]
+            for _ in range(26):
+                states.append(oracle.jacobi5(states[-1], 1))
+            ring = np.ones((H, W), dtype=bool)
+            ring[1:-1, 1:-1] = False
+            for m in range(0, 27):
+                say(f"chain-last abi schedule={schedule} {H}x{W} m={m}")
+                a = torch.from_numpy(a0.copy()).cuda()
+                b = torch.from_numpy(b0.copy()).cuda()
+                _lib.call("sten_sweep_chain_last_f64", a.data_ptr(), b.data_ptr(), H, W, W, m, 0.25,
+                          torch.cuda.current_stream().cuda_stream)
+                last, other = (b, a) if m % 2 else (a, b)
+                if m == 0:
+                    assert np.array_equal(to_host(a), a0) and np.array_equal(to_host(b), b0)
+                    continue
+                assert np.array_equal(to_host(last), states[m]), (schedule, H, W, m)
+                assert np.array_equal(to_host(other)[ring], a0[ring]), (schedule, H, W, m)
+    finally:
+        ops.set_schedule(0)
