@@ -148,13 +148,17 @@ sten_status sten_sweep_chain_f64(double* a, double* b, int64_t H, int64_t W, int
 
 /* The same m sweeps when iterate m-1 is not needed afterwards (the lazy
  * frontend uses it when the next recorded node overwrites the other array's
- * whole interior, Section III-B): iterate m lands in the array sweep m writes
- * (b for odd m, a for even m), with the same bits as sten_sweep_chain_f64;
- * the other array's interior is left unspecified and its ring untouched. All
- * m sweeps run as blocked launches, so the chain costs no extra single-sweep
- * pass. Arguments, checks and status codes as sten_sweep_chain_f64. */
+ * whole interior, Section III-B). All m sweeps run as the fewest blocked
+ * launches the plain schedule allows (sten_tune_schedule); iterate m lands in
+ * the array the last of them writes, with the same bits as
+ * sten_sweep_chain_f64, and *lands_in_b (host memory, written before the call
+ * returns) says which: 1 for b, 0 for a. The other array's interior is left
+ * unspecified; both rings are untouched. Without blocked launches (see
+ * sten_sweep_chain_f64) iterate m lands as after m single sweeps (b for odd
+ * m). lands_in_b NULL: STEN_ERR_PTR; other arguments, checks and status codes
+ * as sten_sweep_chain_f64. */
 sten_status sten_sweep_chain_last_f64(double* a, double* b, int64_t H, int64_t W, int64_t ld, int32_t m, double c,
-                                      hipStream_t stream);
+                                      int32_t* lands_in_b, hipStream_t stream);
 
 /*
  * Temporal blocking (the same method, a different schedule): each launch

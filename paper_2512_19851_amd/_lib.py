@@ -97,7 +97,7 @@ SIGNATURES = {
     "sten_tiled_workspace_bytes": (_sz, [_i64, _i64, _i32, _i32]),
     "sten_tiled_create": (ctypes.c_int, [_i64, _i64, _i32, _i32, _vp, _sz, ctypes.POINTER(_vp)]),
     "sten_sweep_chain_f64": (ctypes.c_int, [_vp, _vp, _i64, _i64, _i64, _i32, _f64, _vp]),
-    "sten_sweep_chain_last_f64": (ctypes.c_int, [_vp, _vp, _i64, _i64, _i64, _i32, _f64, _vp]),
+    "sten_sweep_chain_last_f64": (ctypes.c_int, [_vp, _vp, _i64, _i64, _i64, _i32, _f64, _vp, _vp]),
     "sten_cavity_pressure_f64": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _i64, _i64, _i32, _f64, _f64, _f64, _i32,
                                                 _vp]),
     "sten_tune_pressure": (ctypes.c_int, [_i32]),

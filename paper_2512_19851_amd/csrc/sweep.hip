@@ -512,14 +512,18 @@ sten_status run_sweep_once(const T* src, T* dst, int64_t H, int64_t W, int64_t l
 void launch_sweep_f64_internal(const double* in, double* out, int H, int W, int64_t ld, double c, hipStream_t s);
 
 // m sweeps ping-ponging between a and b from a (the listing's loop on two
-// arrays with equal rings): the first m-1 as blocked launches that end in the
-// array iterate m-1 belongs to, then one plain sweep into the other array.
-// keep_prev: the other array ends holding iterate m-1 (else its interior is left unspecified, and all m
-// sweeps run blocked)
+// arrays with equal rings). keep_prev: the first m-1 as blocked launches that
+// end in the array iterate m-1 belongs to, then one plain sweep into the other
+// array, so both iterates are kept. Otherwise (lands_in_b not null) all m
+// sweeps run as the fewest blocked launches, iterate m lands in whichever
+// array the last one writes (*lands_in_b: 1 for b, 0 for a), and the other
+// array's interior is left unspecified.
 sten_status run_chain_f64(double* a, double* b, int64_t H, int64_t W, int64_t ld, int32_t m, double c, bool keep_prev,
-                          hipStream_t stream) {
+                          int32_t* lands_in_b, hipStream_t stream) {
+    if (!keep_prev && lands_in_b == nullptr) return STEN_ERR_PTR;
     if (H < 0 || W < 0 || (H > 0 && ld < W) || m < 0 || H > INT32_MAX / 2 || W > INT32_MAX / 2)
         return STEN_ERR_ARG;
+    if (!keep_prev) *lands_in_b = m % 2;  // the single-sweep parity, kept for no-op calls
     if (m == 0 || H < 3 || W < 3) return STEN_OK;
     if (a == nullptr || b == nullptr) return STEN_ERR_PTR;
     const size_t span = span_bytes(H, W, ld, sizeof(double));
@@ -536,7 +540,8 @@ sten_status run_chain_f64(double* a, double* b, int64_t H, int64_t W, int64_t ld
         // k launches; launch j writes b for odd j, a for even j, and the k-th must write the array
         // that holds iterate n (b when n is odd), so k and n have the same parity
         int k = (n + L - 1) / L;
-        if (k % 2 != n % 2) ++k;
+        if (keep_prev && k % 2 != n % 2) ++k;
+        else if (!keep_prev) *lands_in_b = k % 2;
         const int base = n / k, extra = n % k;
         for (int j = 1; j <= k; ++j) {
             double* dst = (j % 2) ? b : a;
@@ -642,12 +647,12 @@ sten_status sten_fill_rect_f64(double* grid, int64_t H, int64_t W, int64_t ld, i
 
 sten_status sten_sweep_chain_f64(double* a, double* b, int64_t H, int64_t W, int64_t ld, int32_t m, double c,
                                  hipStream_t stream) {
-    return sten::run_chain_f64(a, b, H, W, ld, m, c, true, stream);
+    return sten::run_chain_f64(a, b, H, W, ld, m, c, true, nullptr, stream);
 }
 
 sten_status sten_sweep_chain_last_f64(double* a, double* b, int64_t H, int64_t W, int64_t ld, int32_t m, double c,
-                                      hipStream_t stream) {
-    return sten::run_chain_f64(a, b, H, W, ld, m, c, false, stream);
+                                      int32_t* lands_in_b, hipStream_t stream) {
+    return sten::run_chain_f64(a, b, H, W, ld, m, c, false, lands_in_b, stream);
 }
 
 sten_status sten_sweep_f64(const double* src, double* dst, int64_t H, int64_t W, int64_t ld, double c,

@@ -48,6 +48,7 @@ for all ASTs (Section III-C).
 
 from __future__ import annotations
 
+import ctypes
 import itertools
 import struct
 from dataclasses import dataclass, field
@@ -242,7 +243,9 @@ class Array:
 
     def tensor(self):
         """The array's data after everything queued so far has run (syncs the context). The caller may
-        write to it, so the frontend forgets what it knew of the array's ring."""
+        write to it, so the frontend forgets what it knew of the array's ring. Later operations may move
+        the array to another buffer (Jacobi chains exchange the buffers of their two arrays): call tensor()
+        again to see their results."""
         self.ctx.sync()
         self.ctx.invalidate(self)
         return self.data
@@ -591,6 +594,20 @@ def split_for_limits(nodes: list) -> list:
     return progs
 
 
+def swap_chain_buffers(chain: list, lands_in_b: bool) -> None:
+    """After a chain that produced only its last iterate: if the iterate landed in the buffer of the array
+    that one node at a time would have left iterate m-1 in, the two arrays exchange buffers, so that the
+    chain's last node's output array holds it. Both arrays carry the same ring (a chain's precondition)
+    and the other one's interior is dead, so nothing a program can read changes; only a buffer handed out
+    earlier by tensor() no longer belongs to the same array (tensor() is to be called again after more
+    operations)."""
+    a = match_jacobi(chain[0])[0]
+    b = chain[0].out
+    m = len(chain)
+    if lands_in_b != bool(m % 2):
+        a.data, b.data = b.data, a.data
+
+
 # ---------------------------------------------------------------------------
 # GPU backend (libsten)
 # ---------------------------------------------------------------------------
@@ -662,7 +679,8 @@ class GpuBackend:
 
     def run_chain(self, chain: list, keep_previous: bool = True) -> None:
         """Jacobi nodes ping-ponging between two arrays with equal rings: one libsten chain call. Without
-        keep_previous only the last iterate is produced (the other array's interior is left unspecified)."""
+        keep_previous only the last iterate is produced, by the fewest blocked launches; when those leave it
+        in the other array, the two arrays exchange buffers (swap_chain_buffers)."""
         from . import _lib
         from .ops import _ld, _stream_ptr
 
@@ -673,8 +691,14 @@ class GpuBackend:
             for n in chain:
                 self.run([n])
             return
-        fn = "sten_sweep_chain_f64" if keep_previous else "sten_sweep_chain_last_f64"
-        _lib.call(fn, a.data.data_ptr(), b.data.data_ptr(), H, W, _ld(a.data), len(chain), float(c), _stream_ptr())
+        if keep_previous:
+            _lib.call("sten_sweep_chain_f64", a.data.data_ptr(), b.data.data_ptr(), H, W, _ld(a.data), len(chain),
+                      float(c), _stream_ptr())
+            return
+        lands_in_b = ctypes.c_int32(0)
+        _lib.call("sten_sweep_chain_last_f64", a.data.data_ptr(), b.data.data_ptr(), H, W, _ld(a.data), len(chain),
+                  float(c), ctypes.byref(lands_in_b), _stream_ptr())
+        swap_chain_buffers(chain, bool(lands_in_b.value))
 
     def synchronize(self) -> None:
         self.torch.cuda.synchronize()

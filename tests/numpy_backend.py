@@ -17,6 +17,7 @@ class NumpyBackend:
     def __init__(self, chain_levels: int = 10):
         self.groups = []
         self.chains = []
+        self.swaps = 0
         self.chain_levels = chain_levels
 
     def alloc(self, shape):
@@ -49,11 +50,12 @@ class NumpyBackend:
             n.out.data[r0:r1, c0:c1] = v
 
     def run_chain(self, chain, keep_previous=True):
-        """A model of the library's chain plan on the CPU: the first m-1 sweeps as k blocked passes (each pass
-        is `lev` sweeps of the oracle from the pass's source, that array's ring at every level), k chosen with
-        the parity that ends in the array of iterate m-1, then one plain sweep. Without keep_previous all m
-        sweeps run as blocked passes and the other array's interior is then poisoned with NaN, so that a
-        result that depended on it would show."""
+        """A model of the library's chain plans on the CPU. Both iterates kept: the first m-1 sweeps as k
+        blocked passes (each pass is `lev` sweeps of the oracle from the pass's source, that array's ring at
+        every level), k chosen with the parity that ends in the array of iterate m-1, then one plain sweep.
+        Last iterate only: all m sweeps as the fewest passes, the arrays exchanging buffers when those end
+        in the other array (as the GPU backend does), and the dead array's interior then poisoned with NaN,
+        so that a result that depended on it would show."""
         a, c = fe.match_jacobi(chain[0])
         b = chain[0].out
         m = len(chain)
@@ -63,7 +65,7 @@ class NumpyBackend:
         src = a
         if L > 1 and n >= 2:
             k = -(-n // L)
-            if k % 2 != n % 2:
+            if keep_previous and k % 2 != n % 2:
                 k += 1
             base, extra = divmod(n, k)
             for j in range(1, k + 1):
@@ -76,11 +78,14 @@ class NumpyBackend:
                 dst = b if j % 2 else a
                 dst.data[1:-1, 1:-1] = oracle.jacobi5(src.data, 1, c)[1:-1, 1:-1]
                 src = dst
-        other = b if src is a else a
         if keep_previous:
+            other = b if src is a else a
             other.data[1:-1, 1:-1] = oracle.jacobi5(src.data, 1, c)[1:-1, 1:-1]
-        else:
-            other.data[1:-1, 1:-1] = np.nan
+            return
+        fe.swap_chain_buffers(chain, src is b)
+        self.swaps += int((src is b) != bool(m % 2))
+        dead = a if m % 2 else b  # the array one node at a time would leave iterate m-1 in
+        dead.data[1:-1, 1:-1] = np.nan
 
     def synchronize(self):
         pass

@@ -205,6 +205,8 @@ def test_listing_chain_skips_dead_iterate():
         w1, w2 = numpy_listing_pair(9, 12, T)
         assert np.array_equal(u1.data, w1) and np.array_equal(u2.data, w2), (depth, T)
         assert ctx.stats["chains_last_only"] > 0 and any(m < 0 for m in be.chains)
+        if depth == 10:  # chains of 10 sweeps: one pass of 10 levels, which ends in the other array
+            assert be.swaps > 0
 
 
 def _jac(dst, src):

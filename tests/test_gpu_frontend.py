@@ -157,8 +157,11 @@ def test_sweep_chain_abi(schedule):
 
 @pytest.mark.parametrize("schedule", [0, 1, 2, 12])
 def test_sweep_chain_last_abi(schedule):
-    """sten_sweep_chain_last_f64: iterate m in the array sweep m writes, bit for bit, for every chain length
-    0..26 (all sweeps as blocked launches); both rings untouched; the other array's interior is free."""
+    """sten_sweep_chain_last_f64: iterate m, bit for bit, in the array the call reports (the one the fewest
+    blocked launches end in: b after an odd number of them), for every chain length 0..26; both rings
+    untouched; the other array's interior is free."""
+    import ctypes
+
     import torch
 
     device()
@@ -175,17 +178,24 @@ def test_sweep_chain_last_abi(schedule):
                 states.append(oracle.jacobi5(states[-1], 1))
             ring = np.ones((H, W), dtype=bool)
             ring[1:-1, 1:-1] = False
+            lands = set()
             for m in range(0, 27):
                 say(f"chain-last abi schedule={schedule} {H}x{W} m={m}")
                 a = torch.from_numpy(a0.copy()).cuda()
                 b = torch.from_numpy(b0.copy()).cuda()
+                in_b = ctypes.c_int32(-1)
                 _lib.call("sten_sweep_chain_last_f64", a.data_ptr(), b.data_ptr(), H, W, W, m, 0.25,
-                          torch.cuda.current_stream().cuda_stream)
-                last, other = (b, a) if m % 2 else (a, b)
+                          ctypes.byref(in_b), torch.cuda.current_stream().cuda_stream)
+                assert in_b.value in (0, 1)
                 if m == 0:
+                    assert in_b.value == 0
                     assert np.array_equal(to_host(a), a0) and np.array_equal(to_host(b), b0)
                     continue
+                last, other = (b, a) if in_b.value else (a, b)
+                lands.add((m % 2, in_b.value))
                 assert np.array_equal(to_host(last), states[m]), (schedule, H, W, m)
                 assert np.array_equal(to_host(other)[ring], a0[ring]), (schedule, H, W, m)
+            if schedule != 1 and min(H, W) >= 64 and W % 2 == 0:
+                assert (0, 1) in lands  # an even chain in one blocked launch ends in b
     finally:
         ops.set_schedule(0)
