@@ -310,7 +310,7 @@ class Context:
         # cheap precondition of a chain here (whole interior, one other array with the same known ring);
         # the Jacobi pattern itself is matched at flush time
         node.chain_ok = out.ring is not None and region == (1, H - 1, 1, W - 1) and len(ins) > 0 and \
-            all(a is ins[0] for a in ins) and ins[0].ring == out.ring and None not in out.ring
+            ins.count(ins[0]) == len(ins) and ins[0].ring == out.ring and None not in out.ring
         self._update_ring(out, region, expr)
         in_uids = {a.uid for a in ins}
         for u in in_uids:                                       # true dependences (read after write)
@@ -460,8 +460,26 @@ def _flatten_sum(e: Expr) -> list:
     return terms[::-1]
 
 
+_JACOBI_MATCH: dict = {}
+_MISSING = object()
+
+
 def match_jacobi(node: Node):
-    """c * (((N + S) + W) + E) on the output region -> (array, c) or None."""
+    """c * (((N + S) + W) + E) on the output region -> (array, c) or None. The parameterised AST text
+    (structure, constants, which array each reference names and its region) and the output region
+    decide the match, so the answer is remembered per (AST, region)."""
+    key = (node.ast, node.region)
+    c = _JACOBI_MATCH.get(key, _MISSING)
+    if c is _MISSING:
+        m = _match_jacobi_tree(node)
+        c = None if m is None else m[1]
+        if len(_JACOBI_MATCH) > 65536:
+            _JACOBI_MATCH.clear()
+        _JACOBI_MATCH[key] = c
+    return None if c is None else (node.ins[0], c)
+
+
+def _match_jacobi_tree(node: Node):
     e = node.expr
     if not (isinstance(e, BinOp) and e.op == "*" and isinstance(e.a, Const)):
         return None
