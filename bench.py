@@ -797,6 +797,36 @@ def bench_adjoint(T: int, args) -> dict:
     }
 
 
+def graph_replay_step(ops, u0, T: int, out, work, steps: int, eager_sec: float) -> dict:
+    """The plain step (ring copy + blocked launches) captured once in a HIP graph and replayed: wall time per
+    replay, and the replays' result against the eager step's bits (the output is cleared between replays)."""
+    import torch
+
+    ref = out.clone()
+    ops.jacobi5(u0, T, out=ref, work=work)
+    gs = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=gs):
+        ops.jacobi5(u0, T, out=out, work=work)
+    same = True
+    for _ in range(3):
+        out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        same = same and bool(torch.equal(out, ref))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    same = same and bool(torch.equal(out, ref))
+    del g
+    return {"ms_per_step": round(sec * 1e3, 4), "vs_eager_calls": round(eager_sec / sec, 3),
+            "bit_identical_to_eager": same,
+            "note": "one step (ring copy + the blocked launches) captured with torch.cuda.graph and replayed; "
+                    "the headline value is the eager calls"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -975,6 +1005,13 @@ def main() -> int:
     single_sec_per_step = (time.perf_counter() - t0) / args.steps
     ops.set_schedule(0)
 
+    log("[bench] the same step captured in a HIP graph and replayed")
+    try:
+        graph_replay = graph_replay_step(ops, u0, T, out, work, args.steps, sec_per_step)
+    except Exception as e:  # reported, never fatal to the benchmark line
+        torch.cuda.synchronize()
+        graph_replay = {"error": f"{type(e).__name__}: {e}"}
+
     log(f"[bench] per-launch kernel timing, {args.kernel_reps} launches")
     a = out.clone()
     b = work
@@ -1109,6 +1146,7 @@ def main() -> int:
         "point_sweeps_per_s": round(interior * T / sec_per_step, 1),
         "roofline": roofline,
         "single_sweep_roofline": single,
+        "graph_replay": graph_replay,
     }
 
     if not args.no_extensions:
