@@ -183,7 +183,7 @@ struct RegShape {
 };
 
 // The smallest lane tile that covers the grid: V = ceil(W / 64) columns and
-// R = ceil(H / waves) rows per lane (rounded up to a row count with a kernel
+// R = ceil(H / waves) rows per lane (every row count 1..16 has a kernel
 // variant). Every lane computes its whole tile each
 // sweep (points past the grid are computed and dropped), so sweep time
 // follows V * R, not the grid's point count: a tight tile keeps a 130 x 130
@@ -192,10 +192,8 @@ __device__ __host__ inline RegShape reg_shape(int H, int W, int block) {
     const int nw = block / 64;
     RegShape s{0, 0};
     const int v = (W + 63) / 64;
-    int r = (H + nw - 1) / nw;
+    const int r = (H + nw - 1) / nw;
     if (v < 1 || v > kRegMaxV || r < 1 || r > kRegMaxR) return s;
-    // row counts with a kernel variant: 1..8, 10, 12, 16 (all 16 spill when inlined together)
-    if (r > 8) r = r <= 10 ? 10 : (r <= 12 ? 12 : 16);
     s.V = v;
     s.R = r;
     return s;
@@ -321,7 +319,8 @@ __device__ __forceinline__ void run_reg_any(const Desc& d, int T, float c, float
     case V_ * 32 + R_: run_reg<V_, R_>(d, T, c, lds); break;
 #define STEN_REG_ROWS(V_)                                                                                     \
     STEN_REG_CASE(V_, 1) STEN_REG_CASE(V_, 2) STEN_REG_CASE(V_, 3) STEN_REG_CASE(V_, 4) STEN_REG_CASE(V_, 5)   \
-    STEN_REG_CASE(V_, 6) STEN_REG_CASE(V_, 7) STEN_REG_CASE(V_, 8) STEN_REG_CASE(V_, 10) STEN_REG_CASE(V_, 12) \
+    STEN_REG_CASE(V_, 6) STEN_REG_CASE(V_, 7) STEN_REG_CASE(V_, 8) STEN_REG_CASE(V_, 9) STEN_REG_CASE(V_, 10)   \
+    STEN_REG_CASE(V_, 11) STEN_REG_CASE(V_, 12) STEN_REG_CASE(V_, 13) STEN_REG_CASE(V_, 14) STEN_REG_CASE(V_, 15) \
     STEN_REG_CASE(V_, 16)
         STEN_REG_ROWS(1) STEN_REG_ROWS(2) STEN_REG_ROWS(3) STEN_REG_ROWS(4)
 #undef STEN_REG_ROWS
