@@ -100,7 +100,8 @@ def test_in_place_rejected_on_gpu(fe):
 
 
 @pytest.mark.parametrize("shape,T,depth", [((64, 64), 25, 1000), ((300, 517), 23, 7), ((257, 1030), 31, 1000),
-                                           ((3, 130), 5, 1000), ((1000, 1000), 40, 12)])
+                                           ((3, 130), 5, 1000), ((1000, 1000), 40, 12), ((512, 1024), 50, 10),
+                                           ((130, 256), 33, 3)])
 def test_listing_chains_keep_both_arrays(fe, shape, T, depth):
     """The listing's Jacobi nodes run as chains of blocked launches; both arrays end as after one node at a
     time (iterate T and iterate T-1)."""
@@ -114,8 +115,12 @@ def test_listing_chains_keep_both_arrays(fe, shape, T, depth):
         u2[1:-1, 1:-1] = 0.25 * (u1[:-2, 1:-1] + u1[2:, 1:-1] + u1[1:-1, :-2] + u1[1:-1, 2:])
         u1, u2 = u2, u1
     say(f"frontend chains {shape} T={T} depth={depth}")
+    ptrs = {u1.data.data_ptr(), u2.data.data_ptr()}
     ctx.sync()
     assert ctx.stats["chained_nodes"] > 0 or H < 3
+    assert {u1.data.data_ptr(), u2.data.data_ptr()} == ptrs  # buffers may be exchanged, never replaced
+    if depth in (3, 10, 12):  # flushes caused by the next Jacobi node: chains that keep only iterate m
+        assert ctx.stats["chains_last_only"] > 0
     u0 = unit_ring_grid(H, W)
     assert np.array_equal(to_host(u1.tensor()), oracle.jacobi5(u0, T))
     assert np.array_equal(to_host(u2.tensor()), oracle.jacobi5(u0, T - 1))
