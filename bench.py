@@ -57,9 +57,15 @@ TB_SRC = [os.path.join(ROOT, "paper_2512_19851_amd", "csrc", "temporal.hip"),
 PRESSURE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pressure_stream_f64_16384_traffic.json")
 PRESSURE_SRC = [os.path.join(ROOT, "paper_2512_19851_amd", "csrc", "pressure.hip"),
                 os.path.join(ROOT, "paper_2512_19851_amd", "csrc", "stream_common.hpp")]
-TB_CAP = 12     # most sweeps per launch of the built-in FP64 schedule
+TB_CAP = 12     # most sweeps per launch of the built-in FP64 schedule while one grid is at most 128 MiB
+TB_CAP_DEEP = 14  # ... and above that (the pair of buffers no longer fits the 256 MiB Infinity Cache)
 TB_LEVELS = 11  # sweeps per launch of the dominant kernel: 100 sweeps run as one launch of 12 and eight of 11
 PREWARM_S = 0.25  # seconds of untimed steps before the timed region
+
+
+def tb_cap(n: int) -> int:
+    """Most sweeps per launch of the library's built-in FP64 schedule for an n x n grid."""
+    return TB_CAP if n * n * 8 <= (128 << 20) else TB_CAP_DEEP
 
 
 def log(msg: str) -> None:
@@ -1018,11 +1024,14 @@ def main() -> int:
     b.copy_(a)
     # The step's launches, timed live: the HIP events that bracket the timed steps on the launch stream,
     # divided by the blocked launches per step (the step's kernels are these launches plus a ring copy of
-    # a few microseconds). T sweeps run as ceil(T / TB_CAP) launches, the sweeps split evenly.
-    launches = -(-T // TB_CAP)
+    # a few microseconds). T sweeps run as ceil(T / cap) launches, the sweeps split evenly.
+    cap = tb_cap(n)
+    launches = -(-T // cap)
     base, extra = divmod(T, launches)
-    mix = ([f"sweep_stream_kernel<double,2,{base + 1},4> x{extra}"] if extra else []) + \
-        [f"sweep_stream_kernel<double,2,{base},4> x{launches - extra}"]
+    def kname(lev: int) -> str:
+        return f"sweep_stream_deep_kernel<{lev}>" if lev > TB_CAP else f"sweep_stream_kernel<double,2,{lev},4>"
+
+    mix = ([f"{kname(base + 1)} x{extra}"] if extra else []) + [f"{kname(base)} x{launches - extra}"]
     step_launch_ms = ev_ms / args.steps / launches
     step_launch_flop = FLOP_PER_POINT * interior * T / launches
     tflops = step_launch_flop / (step_launch_ms * 1e-3) / 1e12
@@ -1136,8 +1145,8 @@ def main() -> int:
             "workload": f"plain FP64 five-point Jacobi, {n}x{n} grid N(0,1) seed 0, {T} sweeps per step",
             "grid": [n, n],
             "sweeps_per_step": T,
-            "schedule": f"temporal blocking, up to {TB_CAP} sweeps per launch, the {T} sweeps split evenly over "
-                        f"{-(-T // TB_CAP)} launches (bit-identical to one sweep per launch)",
+            "schedule": f"temporal blocking, up to {tb_cap(n)} sweeps per launch, the {T} sweeps split evenly over "
+                        f"{-(-T // tb_cap(n))} launches (bit-identical to one sweep per launch)",
             "flop_per_point_per_sweep": FLOP_PER_POINT,
             "bytes_per_point_per_sweep": 16,
             "parallelism": "single GPU",

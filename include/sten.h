@@ -106,7 +106,7 @@ int sten_last_hip_error(void);
  * Bit-exact with the sweep evaluated in FP64 in the listing's order (no fused
  * multiply-add, no reassociation). Schedule: when the three grids are 16-byte
  * aligned with an even ld and T >= 2, several sweeps run per launch
- * (temporal blocking, at most 12 (FP64) or 8-12 (FP32, by grid size) by
+ * (temporal blocking, at most 12-14 (FP64) or 8-12 (FP32) by grid size by
  * default, T split evenly over the launches; see sten_tune_schedule), else one sweep
  * per launch; both give the same bits. Errors: STEN_ERR_ARG, STEN_ERR_PTR,
  * STEN_ERR_ALIAS (any two of u0, out, work overlap), STEN_ERR_HIP.
@@ -165,7 +165,8 @@ sten_status sten_sweep_chain_last_f64(double* a, double* b, int64_t H, int64_t W
  * applies up to `levels` sweeps while reading and writing the grid once, so one
  * pass over HBM serves several sweeps (the T sweeps are split as evenly as
  * ceil(T / levels) launches allow). Two kernels (sten_tune_tb picks one):
- *  - streaming (built-in, levels 1..12): one wave walks down a band of rows
+ *  - streaming (built-in, levels 1..12; FP64 also 13 and 14, at 2 waves per
+ *    SIMD instead of 3): one wave walks down a band of rows
  *    and keeps, for every level, the last two rows it produced; each row of
  *    each level is computed once per band, plus the levels*(levels-1) rows a
  *    band start needs and the column halo of `levels` on each side of a strip;
@@ -186,8 +187,8 @@ sten_status sten_jacobi5_f32_tb(const float* u0, float* out, float* work, int64_
 /* Tuning hook for the temporally blocked kernels. variant: 0 built-in
  * (streaming), 1 register tile (it has launches of 1..6 sweeps; launches of
  * more sweeps, such as those of the plain calls' built-in schedule, still
- * take the streaming kernel, and sten_jacobi5_*_tb accepts levels up to 12
- * under either variant), 2 streaming. band: output rows per streaming
+ * take the streaming kernel, and sten_jacobi5_*_tb accepts levels up to 12,
+ * FP64 up to 14, under either variant), 2 streaming. band: output rows per streaming
  * band (1..65536; 0 built-in: the tallest bands, in whole groups, that let
  * every resident wave slot hold one band). depth: rows the streaming kernel
  * loads ahead of the row it computes (0 or 4, the one depth built). Process-
@@ -206,10 +207,12 @@ sten_status sten_fill_rect_f64(double* grid, int64_t H, int64_t W, int64_t ld, i
                                int64_t c0, int64_t c1, double value, hipStream_t stream);
 
 /* Schedule hook for sten_jacobi5_f64 / _f32: sweeps per launch (1: one sweep
- * per launch, the paper's one kernel per iteration; 2..12: temporal blocking
- * with at most that many; 0: built-in, 12 for FP64, and for FP32 8 while one
- * buffer is at most 128 MiB, else 12). The T sweeps are split evenly over
- * ceil(T / levels) launches. Process-wide. Same bits for every value. */
+ * per launch, the paper's one kernel per iteration; 2..14: temporal blocking
+ * with at most that many, FP32 calls taking at most 12; 0: built-in: while one
+ * buffer is at most 128 MiB (the pair fits the Infinity Cache) 12 for FP64 and
+ * 8 for FP32, above that 14 for FP64 and 12 for FP32). The T sweeps are split
+ * evenly over ceil(T / levels) launches. Process-wide. Same bits for every
+ * value. */
 sten_status sten_tune_schedule(int32_t levels);
 
 /* Tuning hook: output rows per workgroup tile of the sweep kernels (4, 8 or

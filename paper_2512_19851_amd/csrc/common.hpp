@@ -66,6 +66,14 @@ struct GridView {
     int64_t ld;
 };
 
+// Most sweeps per launch of the streaming blocked kernel: FP64 launches of 13
+// and 14 sweeps run at 2 waves per SIMD (their rows do not fit the registers
+// of 3); FP32 stops at 12.
+constexpr int kMaxStreamLevelsF64 = 14;
+constexpr int kMaxStreamLevelsF32 = 12;
+template <typename T>
+constexpr int max_stream_levels() { return sizeof(T) == 8 ? kMaxStreamLevelsF64 : kMaxStreamLevelsF32; }
+
 // Streaming blocked kernel on several FP64 grids at once (temporal.hip), up to
 // kMaxStreamGridsPerLaunch grids per launch.
 constexpr int kMaxStreamGridsPerLaunch = 32;

@@ -415,8 +415,9 @@ std::atomic<int> g_schedule{0};       // sweeps per launch of the plain calls: 0
 // (8192^2: 24% faster than 8).
 template <typename T>
 int default_levels(int64_t H, int64_t W) {
-    if (sizeof(T) == 8) return 12;
-    return H * W * (int64_t)sizeof(T) <= ((int64_t)128 << 20) ? 8 : 12;
+    const bool cached = H * W * (int64_t)sizeof(T) <= ((int64_t)128 << 20);  // the pair fits the 256 MiB MALL
+    if (sizeof(T) == 8) return cached ? 12 : 14;
+    return cached ? 8 : 12;
 }
 
 inline sten_status run_tb_any(const double* u0, double* out, double* work, int64_t H, int64_t W, int64_t ld,
@@ -454,7 +455,7 @@ sten_status run_jacobi5(const T* u0, T* out, T* work, int64_t H, int64_t W, int6
     const int h = (int)H, w = (int)W;
     constexpr int VT = 16 / (int)sizeof(T);
     const int sched = g_schedule.load(std::memory_order_relaxed);
-    const int levels = sched == 0 ? default_levels<T>(H, W) : sched;
+    const int levels = std::min(sched == 0 ? default_levels<T>(H, W) : sched, max_stream_levels<T>());
     if (interior && levels > 1 && T_ >= 2 &&
         ((((uintptr_t)u0 | (uintptr_t)out | (uintptr_t)work) % 16) == 0) && ld % VT == 0) {
         // same bits, fewer passes over HBM: several sweeps per launch
@@ -549,7 +550,7 @@ sten_status run_chain_f64(double* a, double* b, int64_t H, int64_t W, int64_t ld
             if (lev == 1)
                 launch_sweep_f64_internal(src, dst, h, w, ld, c, stream);
             else if (!launch_levels_f64(src, dst, h, w, ld, c, lev, stream))
-                return STEN_ERR_ARG;  // unreachable: 2 <= lev <= L <= 12 and the rows fit the streaming kernel
+                return STEN_ERR_ARG;  // unreachable: 2 <= lev <= L <= 14 and the rows fit the streaming kernel
             src = dst;
         }
     } else {
@@ -678,7 +679,7 @@ sten_status sten_jacobi5_f32(const float* u0, float* out, float* work, int64_t H
 // Schedule hook: sweeps per launch of the plain calls (1: one sweep per
 // launch; 2..12: temporal blocking with that many; 0: built-in).
 sten_status sten_tune_schedule(int32_t levels) {
-    if (levels < 0 || levels > 12) return STEN_ERR_ARG;
+    if (levels < 0 || levels > sten::kMaxStreamLevelsF64) return STEN_ERR_ARG;
     sten::g_schedule = levels;
     return STEN_OK;
 }

@@ -504,8 +504,47 @@ void launch_stream(const T* in, T* out, int H, int W, int64_t ld, T c, hipStream
     sweep_stream_kernel<T, V, TL, D><<<strips * bands, 64, 0, s>>>(in, out, H, W, ld, c, strips, band, flush);
 }
 
+// FP64 launches of 13 or 14 sweeps: the streaming kernel's code at 2 waves
+// per SIMD (its 190-200 VGPRs do not fit 3). Where HBM serves the grid, the
+// deeper pass is faster per sweep than 12 levels at 3 waves; at 4096^2, where
+// the pair of buffers sits in the Infinity Cache, it is not.
+template <int TL>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sweep_stream_deep_kernel(
+    const double* __restrict__ in, double* __restrict__ out, int H, int W, int64_t ld, double c, uint32_t strips,
+    int band, int flush) {
+    stream_tile<double, 2, TL, kStreamDepth>(in, out, H, W, ld, c, strips, band, flush,
+                                             xcd_tile_of_block(blockIdx.x, gridDim.x));
+}
+
+template <int TL>
+void launch_stream_deep(const double* in, double* out, int H, int W, int64_t ld, double c, hipStream_t s) {
+    constexpr int V = 2;
+    constexpr int HALO = (TL + V - 1) / V * V;
+    constexpr int OW = 64 * V - 2 * HALO;
+    const int flush = (W % V == 0 && W >= 64 * V) ? 1 : 0;
+    const uint32_t strips = flush ? ceil_div(W - 64 * V, OW) + 1 : ceil_div(W - 1, OW);
+    int band = g_tb_band.load(std::memory_order_relaxed);
+    if (band <= 0) {
+        static const int waves = resident_waves(reinterpret_cast<const void*>(&sweep_stream_deep_kernel<TL>));
+        const int64_t fit = std::max<int64_t>(1, (waves > 0 ? waves : 1024) / (int64_t)strips);
+        band = (int)std::max<int64_t>(2 * TL, (H - 2 + fit - 1) / fit);
+    }
+    const uint32_t bands = ceil_div(H - 2, band);
+    sweep_stream_deep_kernel<TL><<<strips * bands, 64, 0, s>>>(in, out, H, W, ld, c, strips, band, flush);
+}
+
 template <typename T, int V, int D>
 bool launch_stream_depth(const T* in, T* out, int H, int W, int64_t ld, T c, int levels, hipStream_t s) {
+    if constexpr (sizeof(T) == 8) {
+        if (levels == 13) {
+            launch_stream_deep<13>(in, out, H, W, ld, c, s);
+            return true;
+        }
+        if (levels == 14) {
+            launch_stream_deep<14>(in, out, H, W, ld, c, s);
+            return true;
+        }
+    }
     switch (levels) {
         case 1: launch_stream<T, V, 1, D>(in, out, H, W, ld, c, s); return true;
         case 2: launch_stream<T, V, 2, D>(in, out, H, W, ld, c, s); return true;
@@ -577,7 +616,7 @@ bool launch_stream_grids_depth(const GridView<T>* views, int n, T c, int levels,
     }
 }
 
-// One blocked launch of `levels` sweeps (1..12). The register tile has 1..6
+// One blocked launch of `levels` sweeps (1..12; FP64 1..14). The register tile has 1..6
 // levels: it runs when asked for (variant 1) or when rows are too wide for
 // the streaming kernel, and only for a level count it has. Returns false, with
 // nothing launched, for a level count no kernel has (wide rows: above 6).
@@ -594,7 +633,7 @@ bool launch_levels(const T* in, T* out, int H, int W, int64_t ld, T c, int level
 template <typename T>
 sten_status run_tb(const T* u0, T* out, T* work, int64_t H, int64_t W, int64_t ld, int32_t T_, T c, int32_t tl,
                    hipStream_t stream) {
-    if (tl < 1 || tl > kMaxStreamLevels) return STEN_ERR_ARG;
+    if (tl < 1 || tl > max_stream_levels<T>()) return STEN_ERR_ARG;
     // rows too wide for the streaming kernel's 32-bit offsets take the register tile
     if (W * (int64_t)sizeof(T) >= ((int64_t)1 << 30)) tl = std::min(tl, kMaxBlockLevels);
     const bool interior = H >= 3 && W >= 3;
@@ -636,7 +675,7 @@ bool launch_stream_grids_f64(const GridView<double>* views, int n, double c, int
     return true;
 }
 
-// One blocked launch of `levels` sweeps (1..12) from in to out, FP64 (no
+// One blocked launch of `levels` sweeps (1..14) from in to out, FP64 (no
 // argument checks; 16-byte aligned data, even ld). Returns false, with
 // nothing launched, for a level count no kernel has.
 bool launch_levels_f64(const double* in, double* out, int H, int W, int64_t ld, double c, int levels,

@@ -92,7 +92,7 @@ def jacobi5_tb(u0: torch.Tensor, T: int, c: float = 0.25, levels: int = 2, out: 
 
 
 def set_schedule(levels: int) -> None:
-    """Sweeps per launch of `jacobi5` (1: one per launch; 2..12: temporal blocking; 0: built-in)."""
+    """Sweeps per launch of `jacobi5` (1: one per launch; 2..14: temporal blocking, FP32 at most 12; 0: built-in)."""
     _lib.call("sten_tune_schedule", int(levels))
 
 

@@ -82,8 +82,9 @@ def test_tune_hooks_validate_and_restore(lib):
     assert lib.sten_tune_tb(2, 0, 7) == -1
     assert lib.sten_tune_tb(2, 17, 4) == 0
     assert lib.sten_tune_tb(0, 0, 0) == 0
-    assert lib.sten_tune_schedule(13) == -1
+    assert lib.sten_tune_schedule(15) == -1
     assert lib.sten_tune_schedule(-1) == -1
+    assert lib.sten_tune_schedule(14) == 0
     assert lib.sten_tune_schedule(12) == 0
     assert lib.sten_tune_schedule(0) == 0
     assert lib.sten_tune_tb_rows(5) == -1

@@ -40,6 +40,8 @@ def test_tb_bit_exact(ops, shape, dtype):
     try:
         for name, variant, levels_range in VARIANTS:
             ops.set_tb(variant, 0, 0)
+            if dtype == np.float64:  # FP64 launches of 13 and 14 sweeps (2 waves per SIMD), either variant
+                levels_range = list(levels_range) + [13, 14]
             for levels in levels_range:
                 for T in TS:
                     say(f"tb {name} {dtype.__name__} {shape} levels={levels} T={T}")
@@ -86,18 +88,24 @@ def test_tb_general_coefficient(ops):
 
 
 def test_tb_levels_out_of_range(ops):
-    """1..12 levels under either variant (the register tile hands launches of more than 6 sweeps to
-    the streaming kernel); 0 and 13 are rejected."""
+    """FP64 1..14 and FP32 1..12 levels under either variant (the register tile hands launches of more
+    than 6 sweeps to the streaming kernel); 0, 15 (FP64) and 13 (FP32) are rejected."""
     u = normal_grid(20, 20, seed=1)
     u0 = to_dev(u)
+    u32 = normal_grid(20, 24, seed=2, dtype=np.float32)
+    d32 = to_dev(u32)
     try:
         for variant in (BLOCK, STREAM):
             ops.set_tb(variant, 0, 0)
             assert np.array_equal(to_host(ops.jacobi5_tb(u0, 10, levels=7)), oracle.jacobi5(u, 10))
+            assert np.array_equal(to_host(ops.jacobi5_tb(u0, 28, levels=14)), oracle.jacobi5(u, 28))
+            assert np.array_equal(to_host(ops.jacobi5_tb(d32, 12, levels=12)),
+                                  oracle.jacobi5(u32, 12, dtype=np.float32))
+            for bad in (0, 15):
+                with pytest.raises(ops._lib.StenError):
+                    ops.jacobi5_tb(u0, 10, levels=bad)
             with pytest.raises(ops._lib.StenError):
-                ops.jacobi5_tb(u0, 10, levels=13)
-            with pytest.raises(ops._lib.StenError):
-                ops.jacobi5_tb(u0, 10, levels=0)
+                ops.jacobi5_tb(d32, 10, levels=13)
     finally:
         ops.set_tb(0, 0, 0)
 
@@ -126,6 +134,22 @@ def test_tb_full_size_T100_sampled(ops):
     H, W = u0.shape
     for (i, j) in sample_points(H, W, 32, seed=3, stream=(2, 11)):
         r0, r1, c0, c1 = cone_window(H, W, i, j, T)
+        sub = oracle.jacobi5(u0[r0:r1 + 1, c0:c1 + 1], T)
+        assert got[i, j] == sub[i - r0, j - c0], f"point {(i, j)}"
+
+
+@pytest.mark.parametrize("T", [28, 100])
+def test_f64_deep_schedule_sampled(ops, T):
+    """FP64 through the plain call at 8192^2, where one buffer is past half the MALL and the built-in
+    schedule takes 14 sweeps per launch (2 waves per SIMD): T = 28 is two launches of 14, T = 100 four of
+    13 and four of 12; sampled points, each from its dependence cone, with the deep kernel's band edges
+    (342-row bands) among them."""
+    n = 8192
+    u0 = large_f64(0, n)
+    say(f"f64 {n} T={T} sampled (built-in, deep launches)")
+    got = to_host(ops.jacobi5(to_dev(u0), T))
+    for (i, j) in sample_points(n, n, 24, seed=T, stream=(2, 14, (342, 171))):
+        r0, r1, c0, c1 = cone_window(n, n, i, j, T)
         sub = oracle.jacobi5(u0[r0:r1 + 1, c0:c1 + 1], T)
         assert got[i, j] == sub[i - r0, j - c0], f"point {(i, j)}"
 
