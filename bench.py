@@ -841,6 +841,7 @@ def main() -> int:
     ap.add_argument("--sweeps", type=int, default=100, help="sweeps T per step")
     ap.add_argument("--n", type=int, default=4096, help="grid side")
     ap.add_argument("--kernel-reps", type=int, default=100)
+    ap.add_argument("--levels", type=int, default=TB_LEVELS, help="sweeps per launch in --mode tb")
     ap.add_argument("--cpu-budget", type=float, default=16.0, help="seconds of CPU oracle work")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extensions", action="store_true")
@@ -850,7 +851,7 @@ def main() -> int:
                     help="step: the benchmark; sweep: only --kernel-reps sweep launches; "
                          "copy: only --kernel-reps plain grid copies (counter calibration); "
                          "hilo: only --kernel-reps hi/lo sweeps on encoded grids; "
-                         "tb: only --kernel-reps temporally blocked launches; "
+                         "tb: only --kernel-reps temporally blocked launches of --levels sweeps; "
                          "cavity: only the cavity-flow extension (--n grid side); "
                          "pressure: only --kernel-reps blocked passes of 8 cavity pressure iterations (--n); "
                          "batch: only the batched extension (--sweeps, --steps graph replays); "
@@ -959,14 +960,14 @@ def main() -> int:
             if args.mode == "sweep":
                 ops.sweep(a, b)
             elif args.mode == "tb":
-                ops.jacobi5_tb(a, TB_LEVELS, levels=TB_LEVELS, out=b)  # one blocked launch
+                ops.jacobi5_tb(a, args.levels, levels=args.levels, out=b)  # one blocked launch
             else:
                 ops.jacobi5(a, 0, out=b)  # T = 0: one plain copy of the grid
             a, b = b, a
         e1.record()
         torch.cuda.synchronize()
         per = e0.elapsed_time(e1) / args.kernel_reps
-        moved = {"sweep": launch_bytes, "tb": TB_LEVELS * launch_bytes}.get(args.mode, 16.0 * n * n)
+        moved = {"sweep": launch_bytes, "tb": args.levels * launch_bytes}.get(args.mode, 16.0 * n * n)
         print(json.dumps({"mode": args.mode, "launches": args.kernel_reps, "avg_us": round(per * 1e3, 2),
                           "algorithmic_bytes_per_launch": moved,
                           "GBps": round(moved / (per * 1e-3) / 1e9, 1)}), flush=True)
