@@ -61,11 +61,20 @@ TB_CAP = 12     # most sweeps per launch of the built-in FP64 schedule while one
 TB_CAP_DEEP = 14  # ... and above that (the pair of buffers no longer fits the 256 MiB Infinity Cache)
 TB_LEVELS = 11  # sweeps per launch of the dominant kernel: 100 sweeps run as one launch of 12 and eight of 11
 PREWARM_S = 0.25  # seconds of untimed steps before the timed region
+PRESSURE_MAX_LEVELS = 12  # most cavity pressure iterations per blocked pass (the library's default)
+CAVITY_NIT = 50           # pressure iterations per cavity time step
 
 
 def tb_cap(n: int) -> int:
     """Most sweeps per launch of the library's built-in FP64 schedule for an n x n grid."""
     return TB_CAP if n * n * 8 <= (128 << 20) else TB_CAP_DEEP
+
+
+def pressure_pass_levels(nit: int) -> int:
+    """Iterations in the longest pass when the library splits nit pressure iterations at its default:
+    ceil(nit / 12) passes, as even as they go (50 -> 5 passes of 10)."""
+    passes = -(-nit // PRESSURE_MAX_LEVELS)
+    return -(-nit // passes)
 
 
 def log(msg: str) -> None:
@@ -91,13 +100,14 @@ def source_sha(paths) -> str:
     return hashlib.sha256("\n".join(parts).encode()).hexdigest()[:16]
 
 
-def load_traffic(path: str, src: str):
-    """HBM bytes per launch from committed rocprofv3 counters, if they match the kernel source."""
+def load_traffic(path: str, src: str, **expect):
+    """HBM bytes per launch from committed rocprofv3 counters, if they match the kernel source (and each
+    `expect` key, e.g. the levels per launch the counters were taken at)."""
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("source_sha") != source_sha(src):
+    if rec.get("source_sha") != source_sha(src) or any(rec.get(k) != v for k, v in expect.items()):
         return None
     return rec.get("bytes_per_launch")
 
@@ -625,7 +635,7 @@ def bench_frontend(ops, args) -> dict:
     return res
 
 
-def bench_cavity(args, n: int = 16384, nit: int = 50, steps: int = 2) -> dict:
+def bench_cavity(args, n: int = 16384, nit: int = CAVITY_NIT, steps: int = 2) -> dict:
     """The paper's second application (Section V): lid-driven cavity flow, 16k x 16k per GPU, written
     as slice assignments on the frontend; most nodes run as generated kernels, the u and v updates fused.
     Two pressure solves: the blocked library call (default) and one frontend node per iteration."""
@@ -669,8 +679,8 @@ def bench_cavity(args, n: int = 16384, nit: int = 50, steps: int = 2) -> dict:
         }
         del flow, ctx, u, v, p
     res["blocked_bit_identical_to_per_node"] = all(torch.equal(a, b) for a, b in zip(fields[True], fields[False]))
-    passes = bench_pressure_passes(n, 5)
-    traffic = load_traffic(PRESSURE_TRAFFIC_FILE, PRESSURE_SRC) if n == 16384 else None
+    passes = bench_pressure_passes(n, 5, pressure_pass_levels(nit))
+    traffic = load_traffic(PRESSURE_TRAFFIC_FILE, PRESSURE_SRC, levels=passes["levels"]) if n == 16384 else None
     passes["traffic"] = traffic
     passes["hbm_use_frac"] = (round(traffic / (passes["avg_us_per_call"] * 1e-6) / (HBM_PEAK_GBS * 1e9), 4)
                               if traffic else None)
@@ -682,9 +692,11 @@ def bench_cavity(args, n: int = 16384, nit: int = 50, steps: int = 2) -> dict:
     return res
 
 
-def bench_pressure_passes(n: int, reps: int, levels: int = 8) -> dict:
+def bench_pressure_passes(n: int, reps: int, levels: int = 0) -> dict:
     """`reps` launches of the blocked pressure kernel, each one pass of `levels` cavity pressure iterations
-    on an n x n FP64 grid (N(0,1) p and b, seed 0), timed with HIP events on the launch stream."""
+    (0: the pass of the cavity step's 50, i.e. 10, the LDS-ring kernel) on an n x n FP64 grid (N(0,1) p and
+    b, seed 0), timed with HIP events on the launch stream."""
+    levels = levels or pressure_pass_levels(CAVITY_NIT)
     import torch
 
     from oracle.cavity import CavityParams
@@ -842,6 +854,8 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=4096, help="grid side")
     ap.add_argument("--kernel-reps", type=int, default=100)
     ap.add_argument("--levels", type=int, default=TB_LEVELS, help="sweeps per launch in --mode tb")
+    ap.add_argument("--pressure-levels", type=int, default=0,
+                    help="iterations per pass in --mode pressure (1..12; 0: the cavity step's pass, 10)")
     ap.add_argument("--cpu-budget", type=float, default=16.0, help="seconds of CPU oracle work")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extensions", action="store_true")
@@ -853,7 +867,8 @@ def main() -> int:
                          "hilo: only --kernel-reps hi/lo sweeps on encoded grids; "
                          "tb: only --kernel-reps temporally blocked launches of --levels sweeps; "
                          "cavity: only the cavity-flow extension (--n grid side); "
-                         "pressure: only --kernel-reps blocked passes of 8 cavity pressure iterations (--n); "
+                         "pressure: only --kernel-reps blocked passes of --pressure-levels cavity pressure "
+                         "iterations (--n); "
                          "batch: only the batched extension (--sweeps, --steps graph replays); "
                          "adjoint: only the gradient extension (1024^2, T = 10); "
                          "tiled: only the tiled extension (--n, --sweeps); "
@@ -879,7 +894,7 @@ def main() -> int:
         print(json.dumps({"mode": "cavity", **bench_cavity(args, n=args.n)}), flush=True)
         return 0
     if args.mode == "pressure":
-        print(json.dumps(bench_pressure_passes(args.n, args.kernel_reps)), flush=True)
+        print(json.dumps(bench_pressure_passes(args.n, args.kernel_reps, args.pressure_levels)), flush=True)
         return 0
     if args.mode == "batch":
         from paper_2512_19851_amd import ops

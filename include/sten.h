@@ -232,11 +232,12 @@ sten_status sten_tune_sweep_rows(int32_t rows);
  *            on rows 1..H-2, columns 1..W-2, evaluated in this order;
  *   q[i,W-1] = q[i,W-2], q[i,0] = q[i,1] on rows 1..H-2 (dp/dx = 0);
  *   q[0,:] = q[1,:] (dp/dy = 0, corners included); q[H-1,:] = 0 (the lid).
- * Up to `levels` iterations (1..8; 0 = 8) run per pass over HBM, the nit
- * iterations split as evenly as ceil(nit / levels) passes allow. The result
- * is bit-identical to applying the iteration nit times.
+ * Up to `levels` iterations (1..12; 0 = 12) run per pass over HBM, the nit
+ * iterations split as evenly as ceil(nit / levels) passes allow (50
+ * iterations at the default: 5 passes of 10). The result is bit-identical to
+ * applying the iteration nit times.
  * work: a second H x W buffer, needed when nit > levels (else may be NULL).
- * Errors: STEN_ERR_ARG (negative sizes or nit, ld < W, levels > 8);
+ * Errors: STEN_ERR_ARG (negative sizes or nit, ld < W, levels > 12);
  * STEN_ERR_PTR (NULL or non-device pointers); STEN_ERR_ALIAS (out or work
  * overlapping p0, b or each other); STEN_ERR_UNSUPPORTED for layouts the
  * blocked kernel does not take: H < 3, W < 128, W or ld odd, pointers not

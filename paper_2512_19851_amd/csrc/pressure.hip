@@ -29,6 +29,11 @@
 // Every stored value is the one-iteration-at-a-time value: each point of each
 // level is the same expression on the same operands, evaluated in the same
 // order, without contraction.
+//
+// Passes of more than 8 levels keep the b rows in LDS instead (the register
+// ring no longer fits beside the levels' rows): each b row is loaded into a
+// short register staging ring, written to a per-wave LDS ring of R >= TL rows
+// once it has arrived, and read back once per level.
 #include <algorithm>
 #include <atomic>
 
@@ -44,12 +49,46 @@ constexpr int kPV = 2;  // FP64 values per lane
 constexpr int kPA = 4;  // rows loaded ahead
 
 // BEGIN KERNEL SOURCE (the HBM traffic measurement is keyed to this region)
-template <int TL>
+typedef TVec<double, kPV>::type PVec;
+
+// LB false: b rows in a register ring of PB >= TL + A slots. LB true: b rows
+// staged in PB = P register slots, then kept in an LDS ring of R >= TL rows.
+template <int TL, bool LB>
 struct PressureRing {
-    static constexpr int P = kPA + 2;                  // p rows: step t reads the rows of steps t-2..t
-    static constexpr int PB = (TL + kPA + 5) / 6 * 6;  // b rows: a multiple of 6 and >= TL + A
-    static constexpr int U = PB;                       // group length: a multiple of P, 3 and PB
+    static constexpr int P = kPA + 2;                             // p rows: step t reads the rows of steps t-2..t
+    static constexpr int PB = LB ? P : (TL + kPA + 5) / 6 * 6;    // b rows in registers (a multiple of 6)
+    static constexpr int R = LB ? (TL + 5) / 6 * 6 : 0;           // b rows in LDS: a multiple of 6 and >= TL
+    static constexpr int U = LB ? R : PB;                         // group length: a multiple of P, PB and R
 };
+
+// The b row of step u for one level: from the register ring, or from LDS
+// (row u of the wave's LDS ring; the ring holds 64 lanes x 16 bytes per row).
+template <int TL, bool LB>
+__device__ __forceinline__ void level_b(const double (&bring)[PressureRing<TL, LB>::PB][kPV],
+                                        const PVec* __restrict__ lb, int u, double (&bb)[kPV]) {
+    if constexpr (LB) {
+        const PVec v = lb[(u % PressureRing<TL, LB>::R) * 64 + (int)threadIdx.x];
+        bb[0] = v[0];
+        bb[1] = v[1];
+    } else {
+#pragma unroll
+        for (int e = 0; e < kPV; ++e) bb[e] = bring[u % PressureRing<TL, LB>::PB][e];
+    }
+}
+
+// After step u: the staged b row of step u (arrived by now) goes to LDS row u.
+// Levels read it from step u + 1 on; with R >= TL the row it replaces, step
+// u - R, was last read by level TL at step u - R + TL <= u.
+template <int TL, bool LB>
+__device__ __forceinline__ void stage_b(const double (&bring)[PressureRing<TL, LB>::PB][kPV], PVec* __restrict__ lb,
+                                        int u) {
+    if constexpr (LB) {
+        PVec v;
+        v[0] = bring[u % PressureRing<TL, LB>::PB][0];
+        v[1] = bring[u % PressureRing<TL, LB>::PB][1];
+        lb[(u % PressureRing<TL, LB>::R) * 64 + (int)threadIdx.x] = v;
+    }
+}
 
 // One level of one row from the level below: a and c are its vertical
 // neighbours (in either order), m the row itself, bb the source term.
@@ -93,22 +132,24 @@ __device__ __forceinline__ void pressure_rows(double (&cur)[kPV], double (&prev)
 // loaded for step t - s; t is a constant once the caller's loop is unrolled).
 // w0[k], w1[k] hold the two latest rows of level k >= 1, older first. With
 // NACT == TL the level-TL row goes to `top`.
-template <int TL, int NACT, bool EDGE, bool ROWCHK>
+template <int TL, int NACT, bool EDGE, bool ROWCHK, bool LB>
 __device__ __forceinline__ void pressure_step(double (&w0)[TL][kPV], double (&w1)[TL][kPV], const double (&a0)[kPV],
                                               const double (&b0)[kPV], const double (&x)[kPV],
-                                              double (&bring)[PressureRing<TL>::PB][kPV], double (&top)[kPV], int t,
-                                              int L, int dir, int H, double cw, double cn, double cb, bool fix_lo,
-                                              bool fix_hi) {
-    constexpr int PB = PressureRing<TL>::PB;
+                                              const double (&bring)[PressureRing<TL, LB>::PB][kPV],
+                                              const PVec* __restrict__ lb, double (&top)[kPV], int t, int L, int dir,
+                                              int H, double cw, double cn, double cb, bool fix_lo, bool fix_hi) {
     if constexpr (NACT >= 1) {
         double cur[kPV];
-        pressure_level<EDGE>(a0, b0, x, bring[(t - 1 + PB) % PB], cur, cw, cn, cb, fix_lo, fix_hi);
+        double b1[kPV];
+        level_b<TL, LB>(bring, lb, t - 1, b1);
+        pressure_level<EDGE>(a0, b0, x, b1, cur, cw, cn, cb, fix_lo, fix_hi);
         if constexpr (ROWCHK) pressure_rows<(1 < TL)>(cur, w1[1 < TL ? 1 : 0], L - dir, dir, H);
 #pragma unroll
         for (int s = 2; s <= NACT; ++s) {
             double nv[kPV];
-            pressure_level<EDGE>(w0[s - 1], w1[s - 1], cur, bring[(t - s + 2 * PB) % PB], nv, cw, cn, cb,
-                                 fix_lo, fix_hi);
+            double bs[kPV];
+            level_b<TL, LB>(bring, lb, t - s, bs);
+            pressure_level<EDGE>(w0[s - 1], w1[s - 1], cur, bs, nv, cw, cn, cb, fix_lo, fix_hi);
 #pragma unroll
             for (int e = 0; e < kPV; ++e) {
                 w0[s - 1][e] = w1[s - 1][e];
@@ -136,35 +177,37 @@ __device__ __forceinline__ void pressure_step(double (&w0)[TL][kPV], double (&w1
 }
 
 // Steps 0 .. 2*TL-1: level s is complete from step 2s on.
-template <int TL, int K, bool EDGE>
+template <int TL, int K, bool EDGE, bool LB, typename RG = PressureRing<TL, LB>>
 __device__ __forceinline__ void pressure_prologue(double (&w0)[TL][kPV], double (&w1)[TL][kPV],
-                                                  double (&ring)[PressureRing<TL>::P][kPV],
-                                                  double (&bring)[PressureRing<TL>::PB][kPV],
-                                                  const double* __restrict__ p, const double* __restrict__ b, int L0,
-                                                  int dir, int H, int W, int64_t ld, int j0, double cw, double cn,
-                                                  double cb, bool fix_lo, bool fix_hi) {
-    constexpr int P = PressureRing<TL>::P;
-    constexpr int PB = PressureRing<TL>::PB;
+                                                  double (&ring)[RG::P][kPV], double (&bring)[RG::PB][kPV],
+                                                  PVec* __restrict__ lb, const double* __restrict__ p,
+                                                  const double* __restrict__ b, int L0, int dir, int H, int W,
+                                                  int64_t ld, int j0, double cw, double cn, double cb, bool fix_lo,
+                                                  bool fix_hi) {
+    constexpr int P = RG::P;
+    constexpr int PB = RG::PB;
     if constexpr (K < 2 * TL) {
         double unused[kPV];
-        pressure_step<TL, K / 2, EDGE, true>(w0, w1, ring[(K + P - 2) % P], ring[(K + P - 1) % P], ring[K % P],
-                                             bring, unused, K, L0 + dir * K, dir, H, cw, cn, cb, fix_lo, fix_hi);
+        pressure_step<TL, K / 2, EDGE, true, LB>(w0, w1, ring[(K + P - 2) % P], ring[(K + P - 1) % P],
+                                                 ring[K % P], bring, lb, unused, K, L0 + dir * K, dir, H, cw, cn,
+                                                 cb, fix_lo, fix_hi);
+        stage_b<TL, LB>(bring, lb, K);
         stream_load<double, kPV, 1>(p, L0 + dir * (K + kPA), H, W, ld, j0, ring[(K + kPA) % P]);
         stream_load<double, kPV, 1>(b, L0 + dir * (K + kPA), H, W, ld, j0, bring[(K + kPA) % PB]);
         __builtin_amdgcn_sched_barrier(0);
-        pressure_prologue<TL, K + 1, EDGE>(w0, w1, ring, bring, p, b, L0, dir, H, W, ld, j0, cw, cn, cb, fix_lo,
-                                           fix_hi);
+        pressure_prologue<TL, K + 1, EDGE, LB>(w0, w1, ring, bring, lb, p, b, L0, dir, H, W, ld, j0, cw, cn, cb,
+                                               fix_lo, fix_hi);
     }
 }
 
-template <int TL, bool EDGE>
+template <int TL, bool EDGE, bool LB>
 __device__ __forceinline__ void pressure_band(const double* __restrict__ p, const double* __restrict__ b,
-                                              double* __restrict__ out, int H, int W, int64_t ld, double cw,
-                                              double cn, double cb, int cs, int olo, int ohi, int rb, int re,
-                                              int dir) {
-    constexpr int P = PressureRing<TL>::P;
-    constexpr int PB = PressureRing<TL>::PB;
-    constexpr int U = PressureRing<TL>::U;
+                                              double* __restrict__ out, PVec* __restrict__ lb, int H, int W,
+                                              int64_t ld, double cw, double cn, double cb, int cs, int olo, int ohi,
+                                              int rb, int re, int dir) {
+    constexpr int P = PressureRing<TL, LB>::P;
+    constexpr int PB = PressureRing<TL, LB>::PB;
+    constexpr int U = PressureRing<TL, LB>::U;
     const int lane = threadIdx.x;
     const int j0 = cs + lane * kPV;
     const bool fix_lo = j0 == 0;
@@ -184,7 +227,8 @@ __device__ __forceinline__ void pressure_band(const double* __restrict__ p, cons
         stream_load<double, kPV, 1>(p, L0 + dir * i, H, W, ld, j0, ring[i]);
         stream_load<double, kPV, 1>(b, L0 + dir * i, H, W, ld, j0, bring[i]);
     }
-    pressure_prologue<TL, 0, EDGE>(w0, w1, ring, bring, p, b, L0, dir, H, W, ld, j0, cw, cn, cb, fix_lo, fix_hi);
+    pressure_prologue<TL, 0, EDGE, LB>(w0, w1, ring, bring, lb, p, b, L0, dir, H, W, ld, j0, cw, cn, cb, fix_lo,
+                                       fix_hi);
 
     // Groups of U steps. The bottom and lid rows need per-row handling only in
     // groups whose level rows come within TL rows of them; the last group may
@@ -215,14 +259,17 @@ __device__ __forceinline__ void pressure_band(const double* __restrict__ p, cons
             const bool live = g + i < nsteps;
             double top[kPV];
             if (!rowchk) {
-                pressure_step<TL, TL, EDGE, false>(w0, w1, ring[(t + P - 2) % P], ring[(t + P - 1) % P],
-                                                   ring[t % P], bring, top, t, L, dir, H, cw, cn, cb, fix_lo, fix_hi);
+                pressure_step<TL, TL, EDGE, false, LB>(w0, w1, ring[(t + P - 2) % P], ring[(t + P - 1) % P],
+                                                       ring[t % P], bring, lb, top, t, L, dir, H, cw, cn, cb, fix_lo,
+                                                       fix_hi);
             } else {
-                pressure_step<TL, TL, EDGE, true>(w0, w1, ring[(t + P - 2) % P], ring[(t + P - 1) % P], ring[t % P],
-                                                  bring, top, t, L, dir, H, cw, cn, cb, fix_lo, fix_hi);
+                pressure_step<TL, TL, EDGE, true, LB>(w0, w1, ring[(t + P - 2) % P], ring[(t + P - 1) % P],
+                                                      ring[t % P], bring, lb, top, t, L, dir, H, cw, cn, cb, fix_lo,
+                                                      fix_hi);
                 // the bottom wall: row 0 of the last level is its row 1
                 stream_store<double, kPV, 1>(out, 0, ld, W, live && r == 1, voff_vec, voff_el, top);
             }
+            stage_b<TL, LB>(bring, lb, t);
             stream_load<double, kPV, 1>(p, L + dir * kPA, H, W, ld, j0, ring[(t + kPA) % P]);
             stream_load<double, kPV, 1>(b, L + dir * kPA, H, W, ld, j0, bring[(t + kPA) % PB]);
             stream_store<double, kPV, 1>(out, r, ld, W, live, voff_vec, voff_el, top);
@@ -236,11 +283,11 @@ __device__ __forceinline__ void pressure_band(const double* __restrict__ p, cons
 // [k*OW + HALO, (k+1)*OW + HALO); the last strip loads the last 128 columns
 // and stores [W - 128 + HALO, W). All loads stay inside the grid; the last
 // strip's stores may overlap its neighbour's with the same bits.
-template <int TL>
-__global__ __launch_bounds__(64) void pressure_stream_kernel(const double* __restrict__ p,
-                                                             const double* __restrict__ b, double* __restrict__ out,
-                                                             int H, int W, int64_t ld, double cw, double cn, double cb,
-                                                             uint32_t strips, int band) {
+template <int TL, bool LB>
+__device__ __forceinline__ void pressure_tile(const double* __restrict__ p, const double* __restrict__ b,
+                                              double* __restrict__ out, PVec* __restrict__ lb, int H, int W,
+                                              int64_t ld, double cw, double cn, double cb, uint32_t strips,
+                                              int band) {
     constexpr int HALO = (TL + kPV - 1) / kPV * kPV;
     constexpr int OW = 64 * kPV - 2 * HALO;
     const uint32_t tile = xcd_tile_of_block(blockIdx.x, gridDim.x);
@@ -254,9 +301,28 @@ __global__ __launch_bounds__(64) void pressure_stream_kernel(const double* __res
     const int re = min(rb + band, H - 1);
     const int dir = (bi & 1) ? -1 : 1;
     if (strip == 0 || last)
-        pressure_band<TL, true>(p, b, out, H, W, ld, cw, cn, cb, cs, olo, ohi, rb, re, dir);
+        pressure_band<TL, true, LB>(p, b, out, lb, H, W, ld, cw, cn, cb, cs, olo, ohi, rb, re, dir);
     else
-        pressure_band<TL, false>(p, b, out, H, W, ld, cw, cn, cb, cs, olo, ohi, rb, re, dir);
+        pressure_band<TL, false, LB>(p, b, out, lb, H, W, ld, cw, cn, cb, cs, olo, ohi, rb, re, dir);
+}
+
+// Up to 8 levels: b rows in registers.
+template <int TL>
+__global__ __launch_bounds__(64) void pressure_stream_kernel(const double* __restrict__ p,
+                                                             const double* __restrict__ b, double* __restrict__ out,
+                                                             int H, int W, int64_t ld, double cw, double cn, double cb,
+                                                             uint32_t strips, int band) {
+    pressure_tile<TL, false>(p, b, out, nullptr, H, W, ld, cw, cn, cb, strips, band);
+}
+
+// 9 to 12 levels: b rows in a per-wave LDS ring (R KiB per one-wave workgroup),
+// 2 waves per SIMD.
+template <int TL>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pressure_stream_lds_kernel(
+    const double* __restrict__ p, const double* __restrict__ b, double* __restrict__ out, int H, int W, int64_t ld,
+    double cw, double cn, double cb, uint32_t strips, int band) {
+    __shared__ PVec lb[PressureRing<TL, true>::R * 64];
+    pressure_tile<TL, true>(p, b, out, lb, H, W, ld, cw, cn, cb, strips, band);
 }
 // END KERNEL SOURCE
 
@@ -282,6 +348,8 @@ int resident_waves_of(const void* kernel) {
 // Any band height gives the same results.
 std::atomic<int> g_pressure_band{0};
 
+// Up to 8 levels the register-ring kernel, above that the LDS-ring one (at 8
+// levels the register ring is the faster of the two).
 template <int TL>
 void launch_pressure(const double* p, const double* b, double* out, int H, int W, int64_t ld, double cw, double cn,
                      double cb, hipStream_t s) {
@@ -291,16 +359,21 @@ void launch_pressure(const double* p, const double* b, double* out, int H, int W
     int band = g_pressure_band.load(std::memory_order_relaxed);
     if (band <= 0) {
         // the tallest bands that give every resident wave slot a band (one round), at least 2*TL rows
-        static const int waves = resident_waves_of(reinterpret_cast<const void*>(&pressure_stream_kernel<TL>));
+        static const int waves =
+            TL <= 8 ? resident_waves_of(reinterpret_cast<const void*>(&pressure_stream_kernel<TL <= 8 ? TL : 1>))
+                    : resident_waves_of(reinterpret_cast<const void*>(&pressure_stream_lds_kernel<TL <= 8 ? 9 : TL>));
         const int64_t fit = std::max<int64_t>(1, (waves > 0 ? waves : 1024) / (int64_t)strips);
         band = (int)std::max<int64_t>(2 * TL, (H - 2 + fit - 1) / fit);
     }
     const uint32_t bands = ceil_div(H - 2, band);
-    pressure_stream_kernel<TL><<<strips * bands, 64, 0, s>>>(p, b, out, H, W, ld, cw, cn, cb, strips, band);
+    if constexpr (TL <= 8)
+        pressure_stream_kernel<TL><<<strips * bands, 64, 0, s>>>(p, b, out, H, W, ld, cw, cn, cb, strips, band);
+    else
+        pressure_stream_lds_kernel<TL><<<strips * bands, 64, 0, s>>>(p, b, out, H, W, ld, cw, cn, cb, strips, band);
 }
 
-constexpr int kMaxPressureLevels = 8;
-constexpr int kDefaultPressureLevels = 8;
+constexpr int kMaxPressureLevels = 12;
+constexpr int kDefaultPressureLevels = 12;
 
 void launch_pressure_levels(const double* p, const double* b, double* out, int H, int W, int64_t ld, double cw,
                             double cn, double cb, int levels, hipStream_t s) {
@@ -312,7 +385,11 @@ void launch_pressure_levels(const double* p, const double* b, double* out, int H
         case 5: launch_pressure<5>(p, b, out, H, W, ld, cw, cn, cb, s); break;
         case 6: launch_pressure<6>(p, b, out, H, W, ld, cw, cn, cb, s); break;
         case 7: launch_pressure<7>(p, b, out, H, W, ld, cw, cn, cb, s); break;
-        default: launch_pressure<8>(p, b, out, H, W, ld, cw, cn, cb, s); break;
+        case 8: launch_pressure<8>(p, b, out, H, W, ld, cw, cn, cb, s); break;
+        case 9: launch_pressure<9>(p, b, out, H, W, ld, cw, cn, cb, s); break;
+        case 10: launch_pressure<10>(p, b, out, H, W, ld, cw, cn, cb, s); break;
+        case 11: launch_pressure<11>(p, b, out, H, W, ld, cw, cn, cb, s); break;
+        default: launch_pressure<12>(p, b, out, H, W, ld, cw, cn, cb, s); break;
     }
 }
 

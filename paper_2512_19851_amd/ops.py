@@ -137,7 +137,7 @@ def cavity_pressure(p0: torch.Tensor, b: torch.Tensor, nit: int, cw: float, cn: 
                     out: torch.Tensor | None = None, work: torch.Tensor | None = None,
                     stream=None) -> torch.Tensor:
     """nit pressure iterations of the lid-driven cavity flow (interior update, then the wall conditions), up to
-    `levels` (1..8, 0 = 8) per pass over HBM; bit-identical to one iteration at a time. FP64 grids of one
+    `levels` (1..12, 0 = 12) per pass over HBM; bit-identical to one iteration at a time. FP64 grids of one
     shape and stride. Raises StenError with name STEN_ERR_UNSUPPORTED for layouts the blocked kernel does not
     take (fewer than 3 rows or 128 columns, odd width or stride, unaligned data)."""
     for t, name in ((p0, "p0"), (b, "b")):
@@ -147,7 +147,7 @@ def cavity_pressure(p0: torch.Tensor, b: torch.Tensor, nit: int, cw: float, cn: 
     H, W = p0.shape
     if out is None:
         out = torch.empty_strided(p0.shape, p0.stride(), dtype=p0.dtype, device=p0.device)
-    lev = levels if levels > 0 else 8
+    lev = levels if levels > 0 else 12
     if work is None and nit > lev:
         work = torch.empty_strided(p0.shape, p0.stride(), dtype=p0.dtype, device=p0.device)
     for t, name in ((out, "out"), (work, "work")):

@@ -186,12 +186,13 @@ def test_cavity_pressure_rejects_before_any_hip_call(lib):
     assert f(A, B, O, K, -1, 128, 128, 3, 0.2, 0.3, 0.1, 0, None) == -1   # H < 0
     assert f(A, B, O, K, 8, 128, 127, 3, 0.2, 0.3, 0.1, 0, None) == -1    # ld < W
     assert f(A, B, O, K, 8, 128, 128, -1, 0.2, 0.3, 0.1, 0, None) == -1   # nit < 0
-    assert f(A, B, O, K, 8, 128, 128, 3, 0.2, 0.3, 0.1, 9, None) == -1    # levels > 8
+    assert f(A, B, O, K, 8, 128, 128, 3, 0.2, 0.3, 0.1, 13, None) == -1   # levels > 12
     assert f(A, B, O, K, 0, 128, 128, 3, 0.2, 0.3, 0.1, 0, None) == 0     # empty: no-op
     assert f(None, B, O, K, 8, 128, 128, 3, 0.2, 0.3, 0.1, 0, None) == -3
-    assert f(A, B, O, None, 8, 128, 128, 9, 0.2, 0.3, 0.1, 0, None) == -3  # two passes need work
+    assert f(A, B, O, None, 8, 128, 128, 13, 0.2, 0.3, 0.1, 0, None) == -3  # two passes need work
+    assert f(A, B, O, None, 8, 128, 128, 9, 0.2, 0.3, 0.1, 8, None) == -3   # ... also at 8 levels
     assert f(A, B, A + 64, K, 8, 128, 128, 3, 0.2, 0.3, 0.1, 0, None) == -2  # out overlaps p0
-    assert f(A, B, O, B, 8, 128, 128, 9, 0.2, 0.3, 0.1, 0, None) == -2       # work overlaps b
+    assert f(A, B, O, B, 8, 128, 128, 13, 0.2, 0.3, 0.1, 0, None) == -2      # work overlaps b
     assert f(A, B, O, K, 8, 126, 128, 3, 0.2, 0.3, 0.1, 0, None) == -6      # W < 128
     assert f(A, B, O, K, 8, 129, 130, 3, 0.2, 0.3, 0.1, 0, None) == -6      # odd W
     assert f(A, B, O, K, 2, 128, 128, 3, 0.2, 0.3, 0.1, 0, None) == -6      # H < 3
