@@ -28,7 +28,9 @@
 //    row 0, and no band stores row H-1 (the output's lid row is zeroed once).
 // Every stored value is the one-iteration-at-a-time value: each point of each
 // level is the same expression on the same operands, evaluated in the same
-// order, without contraction.
+// order, without contraction. b does not change during the solve, so the
+// product cb * b[i,j] is formed once per row and pass, as the row is staged:
+// the same rounded value every iteration would form.
 //
 // Passes of more than 8 levels keep the b rows in LDS instead (the register
 // ring no longer fits beside the levels' rows): each b row is loaded into a
@@ -76,33 +78,38 @@ __device__ __forceinline__ void level_b(const double (&bring)[PressureRing<TL, L
     }
 }
 
-// After step u: the staged b row of step u (arrived by now) goes to LDS row u.
-// Levels read it from step u + 1 on; with R >= TL the row it replaces, step
-// u - R, was last read by level TL at step u - R + TL <= u.
-template <int TL, bool LB>
-__device__ __forceinline__ void stage_b(const double (&bring)[PressureRing<TL, LB>::PB][kPV], PVec* __restrict__ lb,
-                                        int u) {
+// After step u, the b row of step u has arrived: it is scaled by cb, in place
+// in the register ring, or on its way to LDS row u. Levels read it from step
+// u + 1 on; with R >= TL the LDS row it replaces, step u - R, was last read by
+// level TL at step u - R + TL <= u.
+template <int TL, bool LB, typename RG = PressureRing<TL, LB>>
+__device__ __forceinline__ void stage_b(double (&bring)[RG::PB][kPV], PVec* __restrict__ lb, int u, double cb) {
+    constexpr int PB = RG::PB;
     if constexpr (LB) {
         PVec v;
-        v[0] = bring[u % PressureRing<TL, LB>::PB][0];
-        v[1] = bring[u % PressureRing<TL, LB>::PB][1];
-        lb[(u % PressureRing<TL, LB>::R) * 64 + (int)threadIdx.x] = v;
+        v[0] = cb * bring[u % PB][0];
+        v[1] = cb * bring[u % PB][1];
+        lb[(u % RG::R) * 64 + (int)threadIdx.x] = v;
+    } else {
+#pragma unroll
+        for (int e = 0; e < kPV; ++e) bring[u % PB][e] = cb * bring[u % PB][e];
     }
 }
 
 // One level of one row from the level below: a and c are its vertical
-// neighbours (in either order), m the row itself, bb the source term.
-// fix_lo / fix_hi: this lane holds column 0 / column W-1 (side-wall copies).
+// neighbours (in either order), m the row itself, sb the scaled source term
+// cb * b. fix_lo / fix_hi: this lane holds column 0 / column W-1 (side-wall
+// copies).
 template <bool EDGE>
 __device__ __forceinline__ void pressure_level(const double (&a)[kPV], const double (&m)[kPV], const double (&c)[kPV],
-                                               const double (&bb)[kPV], double (&res)[kPV], double cw, double cn,
-                                               double cb, bool fix_lo, bool fix_hi) {
+                                               const double (&sb)[kPV], double (&res)[kPV], double cw, double cn,
+                                               bool fix_lo, bool fix_hi) {
     const double lft = lane_from_lower(m[1]);  // column j0 - 1
     const double rgt = lane_from_upper(m[0]);  // column j0 + 2
     const double h0 = m[1] + lft;              // east + west of column j0
     const double h1 = rgt + m[0];              // east + west of column j0 + 1
-    const double v0 = (cw * h0 + cn * (c[0] + a[0])) - cb * bb[0];
-    const double v1 = (cw * h1 + cn * (c[1] + a[1])) - cb * bb[1];
+    const double v0 = (cw * h0 + cn * (c[0] + a[0])) - sb[0];
+    const double v1 = (cw * h1 + cn * (c[1] + a[1])) - sb[1];
     res[0] = (EDGE && fix_lo) ? v1 : v0;
     res[1] = (EDGE && fix_hi) ? v0 : v1;
 }
@@ -137,19 +144,19 @@ __device__ __forceinline__ void pressure_step(double (&w0)[TL][kPV], double (&w1
                                               const double (&b0)[kPV], const double (&x)[kPV],
                                               const double (&bring)[PressureRing<TL, LB>::PB][kPV],
                                               const PVec* __restrict__ lb, double (&top)[kPV], int t, int L, int dir,
-                                              int H, double cw, double cn, double cb, bool fix_lo, bool fix_hi) {
+                                              int H, double cw, double cn, bool fix_lo, bool fix_hi) {
     if constexpr (NACT >= 1) {
         double cur[kPV];
         double b1[kPV];
         level_b<TL, LB>(bring, lb, t - 1, b1);
-        pressure_level<EDGE>(a0, b0, x, b1, cur, cw, cn, cb, fix_lo, fix_hi);
+        pressure_level<EDGE>(a0, b0, x, b1, cur, cw, cn, fix_lo, fix_hi);
         if constexpr (ROWCHK) pressure_rows<(1 < TL)>(cur, w1[1 < TL ? 1 : 0], L - dir, dir, H);
 #pragma unroll
         for (int s = 2; s <= NACT; ++s) {
             double nv[kPV];
             double bs[kPV];
             level_b<TL, LB>(bring, lb, t - s, bs);
-            pressure_level<EDGE>(w0[s - 1], w1[s - 1], cur, bs, nv, cw, cn, cb, fix_lo, fix_hi);
+            pressure_level<EDGE>(w0[s - 1], w1[s - 1], cur, bs, nv, cw, cn, fix_lo, fix_hi);
 #pragma unroll
             for (int e = 0; e < kPV; ++e) {
                 w0[s - 1][e] = w1[s - 1][e];
@@ -190,8 +197,8 @@ __device__ __forceinline__ void pressure_prologue(double (&w0)[TL][kPV], double 
         double unused[kPV];
         pressure_step<TL, K / 2, EDGE, true, LB>(w0, w1, ring[(K + P - 2) % P], ring[(K + P - 1) % P],
                                                  ring[K % P], bring, lb, unused, K, L0 + dir * K, dir, H, cw, cn,
-                                                 cb, fix_lo, fix_hi);
-        stage_b<TL, LB>(bring, lb, K);
+                                                 fix_lo, fix_hi);
+        stage_b<TL, LB>(bring, lb, K, cb);
         stream_load<double, kPV, 1>(p, L0 + dir * (K + kPA), H, W, ld, j0, ring[(K + kPA) % P]);
         stream_load<double, kPV, 1>(b, L0 + dir * (K + kPA), H, W, ld, j0, bring[(K + kPA) % PB]);
         __builtin_amdgcn_sched_barrier(0);
@@ -260,16 +267,16 @@ __device__ __forceinline__ void pressure_band(const double* __restrict__ p, cons
             double top[kPV];
             if (!rowchk) {
                 pressure_step<TL, TL, EDGE, false, LB>(w0, w1, ring[(t + P - 2) % P], ring[(t + P - 1) % P],
-                                                       ring[t % P], bring, lb, top, t, L, dir, H, cw, cn, cb, fix_lo,
+                                                       ring[t % P], bring, lb, top, t, L, dir, H, cw, cn, fix_lo,
                                                        fix_hi);
             } else {
                 pressure_step<TL, TL, EDGE, true, LB>(w0, w1, ring[(t + P - 2) % P], ring[(t + P - 1) % P],
-                                                      ring[t % P], bring, lb, top, t, L, dir, H, cw, cn, cb, fix_lo,
+                                                      ring[t % P], bring, lb, top, t, L, dir, H, cw, cn, fix_lo,
                                                       fix_hi);
                 // the bottom wall: row 0 of the last level is its row 1
                 stream_store<double, kPV, 1>(out, 0, ld, W, live && r == 1, voff_vec, voff_el, top);
             }
-            stage_b<TL, LB>(bring, lb, t);
+            stage_b<TL, LB>(bring, lb, t, cb);
             stream_load<double, kPV, 1>(p, L + dir * kPA, H, W, ld, j0, ring[(t + kPA) % P]);
             stream_load<double, kPV, 1>(b, L + dir * kPA, H, W, ld, j0, bring[(t + kPA) % PB]);
             stream_store<double, kPV, 1>(out, r, ld, W, live, voff_vec, voff_el, top);
