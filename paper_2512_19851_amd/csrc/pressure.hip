@@ -16,7 +16,8 @@
 //  * b: each level reads b at its own row. b rows are loaded with the p rows
 //    (same step, same clamped row) into a ring long enough that the deepest
 //    level still finds its row: level s reads, at step t, the b row loaded for
-//    step t - s, and a slot is reloaded only PB >= TL + A steps later.
+//    step t - s, and a slot is reloaded only PB >= TL + A steps later (up to 8
+//    levels; deeper passes keep the ring in LDS, below).
 //  * side walls: only the grid-aligned strip layout is used (W even, W >= 128),
 //    so column 0 and column 1 sit in lane 0 of the first strip and columns
 //    W-2, W-1 in lane 63 of the last: the copies are lane-local selects.
@@ -63,8 +64,8 @@ struct PressureRing {
     static constexpr int U = LB ? R : PB;                         // group length: a multiple of P, PB and R
 };
 
-// The b row of step u for one level: from the register ring, or from LDS
-// (row u of the wave's LDS ring; the ring holds 64 lanes x 16 bytes per row).
+// The scaled b row (cb * b) of step u for one level: from the register ring,
+// or from LDS (row u of the wave's LDS ring; 64 lanes x 16 bytes per row).
 template <int TL, bool LB>
 __device__ __forceinline__ void level_b(const double (&bring)[PressureRing<TL, LB>::PB][kPV],
                                         const PVec* __restrict__ lb, int u, double (&bb)[kPV]) {

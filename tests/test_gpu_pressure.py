@@ -155,3 +155,29 @@ def test_pressure_beyond_int32_points(ops):
                      prm, nit)
         for levels, v in vals.items():
             assert v[k] == want[i - r0, j - c0], f"point {(i, j)} levels={levels}"
+
+
+@pytest.mark.parametrize("nit,levels", [(20, 0), (25, 0), (17, 8)], ids=["lds-ring", "mixed", "register-ring"])
+def test_pressure_graph_replays(ops, nit, levels):
+    """The blocked pressure call (lid fill kernel + passes, no allocation, no memset) captured in a HIP graph:
+    every replay, with eager work on the output and the work buffer between replays, gives the oracle's bits.
+    Passes: 20 iterations at the default are 10 + 10 (LDS ring); 25 are 9 (LDS ring) + 8 + 8 (register
+    ring); 17 at 8 levels are 6 + 6 + 5 (register ring)."""
+    import torch
+
+    H, W = 300, 516
+    p0, b, prm = _inputs(H, W, seed=33)
+    want = _want(p0, b, prm, nit)
+    dp, db = to_dev(p0), to_dev(b)
+    out = torch.empty_like(dp)
+    work = torch.empty_like(dp)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    say(f"graph capture of the pressure call {H}x{W} nit={nit} levels={levels}")
+    with torch.cuda.graph(g, stream=s):
+        ops.cavity_pressure(dp, db, nit, prm.cw, prm.cn, prm.cb, levels=levels, out=out, work=work)
+    for r in range(4):
+        out.fill_(float("nan"))
+        work.fill_(float("nan"))
+        g.replay()
+        assert np.array_equal(to_host(out), want), r
