@@ -48,3 +48,25 @@ def test_host_cores_is_nproc():
     if out.returncode == 0:
         assert bench.host_cores() == int(out.stdout.strip())
     assert 1 <= bench.host_cores() <= (os.cpu_count() or 1)
+
+
+def test_traffic_record_checks_expected_keys(tmp_path):
+    """A record taken at another pass size (levels) is not used for this one."""
+    src = _kernel_file(tmp_path, "int f(int x) { return x; }\n")
+    rec = tmp_path / "traffic.json"
+    rec.write_text(json.dumps({"source_sha": bench.source_sha(src), "levels": 10, "bytes_per_launch": 7.0}))
+    assert bench.load_traffic(str(rec), src, levels=10) == 7.0
+    assert bench.load_traffic(str(rec), src, levels=8) is None
+    assert bench.load_traffic(str(rec), src) == 7.0
+
+
+def test_pressure_pass_levels_follow_the_library_split():
+    """The longest pass of nit iterations at the library's default: ceil(nit / 12) passes, as even as they
+    go (the first nit % passes passes take one more)."""
+    for nit in range(1, 200):
+        passes = -(-nit // bench.PRESSURE_MAX_LEVELS)
+        base, extra = divmod(nit, passes)
+        sizes = [base + (1 if k < extra else 0) for k in range(passes)]
+        assert sum(sizes) == nit and max(sizes) <= bench.PRESSURE_MAX_LEVELS
+        assert bench.pressure_pass_levels(nit) == max(sizes)
+    assert bench.pressure_pass_levels(bench.CAVITY_NIT) == 10
