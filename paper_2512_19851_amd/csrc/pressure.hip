@@ -359,6 +359,14 @@ std::atomic<int> g_pressure_band{0};
 // Up to 8 levels the register-ring kernel, above that the LDS-ring one (at 8
 // levels the register ring is the faster of the two).
 template <int TL>
+const void* pressure_kernel_of() {
+    if constexpr (TL <= 8)
+        return reinterpret_cast<const void*>(&pressure_stream_kernel<TL>);
+    else
+        return reinterpret_cast<const void*>(&pressure_stream_lds_kernel<TL>);
+}
+
+template <int TL>
 void launch_pressure(const double* p, const double* b, double* out, int H, int W, int64_t ld, double cw, double cn,
                      double cb, hipStream_t s) {
     constexpr int HALO = (TL + kPV - 1) / kPV * kPV;
@@ -367,9 +375,7 @@ void launch_pressure(const double* p, const double* b, double* out, int H, int W
     int band = g_pressure_band.load(std::memory_order_relaxed);
     if (band <= 0) {
         // the tallest bands that give every resident wave slot a band (one round), at least 2*TL rows
-        static const int waves =
-            TL <= 8 ? resident_waves_of(reinterpret_cast<const void*>(&pressure_stream_kernel<TL <= 8 ? TL : 1>))
-                    : resident_waves_of(reinterpret_cast<const void*>(&pressure_stream_lds_kernel<TL <= 8 ? 9 : TL>));
+        static const int waves = resident_waves_of(pressure_kernel_of<TL>());
         const int64_t fit = std::max<int64_t>(1, (waves > 0 ? waves : 1024) / (int64_t)strips);
         band = (int)std::max<int64_t>(2 * TL, (H - 2 + fit - 1) / fit);
     }
