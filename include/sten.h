@@ -358,8 +358,9 @@ typedef struct {
  * sten_expr_log), every load inside its slot's extent (STEN_ERR_ARG), no
  * output overlapping an input extent or another output (STEN_ERR_ALIAS, the
  * paper's rule that an assignment may not read what it writes), device
- * pointers (STEN_ERR_PTR). STEN_ERR_UNSUPPORTED if the run-time compiler
- * fails (log in sten_expr_log). rows or cols == 0: nothing to do. */
+ * pointers (STEN_ERR_PTR), rows < 2^31 and cols < 2^31 - 256 (STEN_ERR_ARG).
+ * STEN_ERR_UNSUPPORTED if the run-time compiler fails (log in sten_expr_log).
+ * rows or cols == 0: nothing to do. */
 sten_status sten_expr_run(const char* program, const sten_expr_in* ins, int32_t nin, const sten_expr_out* outs,
                           int32_t nout, int64_t rows, int64_t cols, hipStream_t stream);
 

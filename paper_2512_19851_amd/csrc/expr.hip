@@ -330,7 +330,8 @@ sten_status sten_expr_run(const char* program, const sten_expr_in* ins, int32_t 
     using namespace sten;
     if (program == nullptr || ins == nullptr || outs == nullptr) return STEN_ERR_ARG;
     if (nin < 1 || nin > kExprMaxIn || nout < 1 || nout > kExprMaxOut || rows < 0 || cols < 0) return STEN_ERR_ARG;
-    if (rows > INT32_MAX || cols > INT32_MAX) return STEN_ERR_ARG;
+    // the kernel forms a block's column indices in 32-bit arithmetic
+    if (rows > INT32_MAX || cols > INT32_MAX - kExprBlock) return STEN_ERR_ARG;
     const int64_t bpr = (cols + kExprBlock - 1) / kExprBlock;
     if (rows * bpr > INT32_MAX) return STEN_ERR_ARG;
     // One lock from parsing to the kernel lookup: the prepared program (owned by the cache) stays valid

@@ -226,6 +226,7 @@ def test_expr_run_rejects_before_any_hip_call(lib):
     assert run(b"L0,0,0", 4, 4) == -2
     outs[0].base = 0x20000000
     assert run(b"L0,0,0", 0, 4) == 0                      # empty region
+    assert run(b"L0,0,0", 1, 2**31 - 200) == -1           # column indices would pass 32 bits
     assert b"expression" in lib.sten_expr_log() or lib.sten_expr_log() == b""
 
 
