@@ -328,7 +328,8 @@ sten_status sten_tune_hilo_variant(int32_t variant);
  * fusion, Section III-B). These calls do that for FP64 slice expressions:
  * the library emits HIP source for a fused group, compiles it with hiprtc for
  * the current device, caches the code object per program and the kernel per
- * device, and launches one thread per output element.
+ * device, and launches one thread per two adjacent output elements of a row
+ * (each operand pair one 16-byte load).
  *
  * Program text: one expression per output, separated by ';', each in postfix
  * form with blank-separated tokens:
@@ -358,7 +359,7 @@ typedef struct {
  * sten_expr_log), every load inside its slot's extent (STEN_ERR_ARG), no
  * output overlapping an input extent or another output (STEN_ERR_ALIAS, the
  * paper's rule that an assignment may not read what it writes), device
- * pointers (STEN_ERR_PTR), rows < 2^31 and cols < 2^31 - 256 (STEN_ERR_ARG).
+ * pointers (STEN_ERR_PTR), rows < 2^31 and cols < 2^31 - 512 (STEN_ERR_ARG).
  * STEN_ERR_UNSUPPORTED if the run-time compiler fails (log in sten_expr_log).
  * rows or cols == 0: nothing to do. */
 sten_status sten_expr_run(const char* program, const sten_expr_in* ins, int32_t nin, const sten_expr_out* outs,

@@ -3,11 +3,18 @@
 //
 // The frontend hands over one fused group of slice assignments with the same
 // output shape as a small postfix program (grammar in sten.h). This file
-// parses and validates it on the host, emits one HIP kernel for it (one thread
-// per output element, as in the paper's generator; every operation rounds once,
-// in program order, with no contraction into fused multiply-adds), compiles it
-// with hiprtc for the device's architecture, caches the code object per
-// program and the loaded function per device, and launches it.
+// parses and validates it on the host, emits one HIP kernel for it (every
+// operation rounds once, in program order, with no contraction into fused
+// multiply-adds), compiles it with hiprtc for the device's architecture,
+// caches the code object per program and the loaded function per device, and
+// launches it.
+//
+// The paper's generator runs one thread per output element. Such kernels are
+// bound by how many vector memory instructions they issue, not by their
+// arithmetic or by HBM, so here a thread computes two adjacent elements of a
+// row and moves each operand pair with one 16-byte load or store (8-byte
+// aligned, which the hardware takes as one instruction); the last column of
+// an odd-width row falls back to single elements.
 //
 // Nothing here touches the GPU until a launch: parsing, validation, source
 // generation and compilation run on any host with ROCm, which is how the CPU
@@ -37,6 +44,7 @@ constexpr int kExprMaxOut = 8;
 constexpr int kExprMaxTokens = 1 << 16;
 constexpr int kExprMaxOffset = 1 << 20;
 constexpr int kExprBlock = 256;
+constexpr int kExprCols = 2;  // adjacent output columns per thread
 
 // Kernel argument block; the generated source declares the same layout.
 struct ExprArgs {
@@ -137,70 +145,120 @@ std::string hex_double(double v) {
     return std::string("(") + buf + ")";
 }
 
-// One kernel for the whole group. Loads are named once per (slot, di, dj);
-// every operation gets its own temporary, so the compiled order is the
-// program's order and each operation rounds once.
+// The postfix program of one output as temporaries appended to `body`; a load
+// token becomes the operand `load(slot, di, dj)` returns. Every operation gets
+// its own temporary, so the compiled order is the program's order and each
+// operation rounds once.
+template <typename LoadName>
+std::string emit_expression(const std::vector<Token>& e, LoadName load, int& tmp, std::string& body) {
+    std::vector<std::string> st;
+    for (const Token& t : e) {
+        switch (t.kind) {
+            case Token::LOAD: st.push_back(load(t.slot, t.di, t.dj)); break;
+            case Token::CONST: st.push_back(hex_double(t.value)); break;
+            case Token::NEG:
+            case Token::SQR: {
+                std::string x = st.back();
+                st.pop_back();
+                std::string name = "t" + std::to_string(tmp++);
+                body += "    const double " + name + " = " + (t.kind == Token::NEG ? "-" + x : x + " * " + x) +
+                        ";\n";
+                st.push_back(name);
+                break;
+            }
+            default: {
+                std::string y = st.back();
+                st.pop_back();
+                std::string x = st.back();
+                st.pop_back();
+                const char* op = t.kind == Token::ADD ? " + " : t.kind == Token::SUB ? " - "
+                               : t.kind == Token::MUL ? " * " : " / ";
+                std::string name = "t" + std::to_string(tmp++);
+                body += "    const double " + name + " = " + x + op + y + ";\n";
+                st.push_back(name);
+            }
+        }
+    }
+    return st.back();
+}
+
+// One kernel for the whole group. A thread owns columns j and j + 1 of row i.
+// With both inside the region, each distinct (slot, di, dj) is one 16-byte
+// load of the pair at columns j + dj, j + dj + 1 (both inside the slot's
+// checked extent), each element is evaluated from its half, and each output
+// pair is one 16-byte store. A thread whose j is the region's last column
+// loads and stores single values.
 std::string generate_source(const Program& prog) {
     std::string s;
     s += "// generated by libsten for one fused group of slice assignments\n";
     s += "struct StenExprArgs { const double* in[" + std::to_string(kExprMaxIn) + "]; long long ldi[" +
          std::to_string(kExprMaxIn) + "]; double* out[" + std::to_string(kExprMaxOut) + "]; long long ldo[" +
          std::to_string(kExprMaxOut) + "]; int rows; int cols; int bpr; int pad; };\n";
+    s += "typedef double sten_pair __attribute__((ext_vector_type(2), aligned(8)));\n";
     s += "extern \"C\" __global__ __launch_bounds__(" + std::to_string(kExprBlock) +
          ") void sten_expr_kernel(StenExprArgs a) {\n";
     s += "  const int b = (int)blockIdx.x;\n";
     s += "  const int i = b / a.bpr;\n";
-    s += "  const int j = (b - i * a.bpr) * " + std::to_string(kExprBlock) + " + (int)threadIdx.x;\n";
+    s += "  const int j = (b - i * a.bpr) * " + std::to_string(kExprBlock * kExprCols) + " + (int)threadIdx.x * " +
+         std::to_string(kExprCols) + ";\n";
     s += "  if (j >= a.cols) return;\n";
     s += "  const long long r = i;\n";
-    std::map<std::tuple<int, int, int>, std::string> loads;
+    auto address = [](int slot, int di, int dj) {
+        return "a.in[" + std::to_string(slot) + "] + (r + (" + std::to_string(di) + ")) * a.ldi[" +
+               std::to_string(slot) + "] + (j + (" + std::to_string(dj) + "))";
+    };
     int tmp = 0;
-    std::string body;
-    for (size_t o = 0; o < prog.outs.size(); ++o) {
-        std::vector<std::string> st;
-        for (const Token& t : prog.outs[o]) {
-            switch (t.kind) {
-                case Token::LOAD: {
-                    auto key = std::make_tuple(t.slot, t.di, t.dj);
-                    auto it = loads.find(key);
-                    if (it == loads.end()) {
-                        std::string name = "l" + std::to_string(loads.size());
-                        s += "  const double " + name + " = a.in[" + std::to_string(t.slot) + "][(r + (" +
-                             std::to_string(t.di) + ")) * a.ldi[" + std::to_string(t.slot) + "] + (j + (" +
-                             std::to_string(t.dj) + "))];\n";
-                        it = loads.emplace(key, name).first;
-                    }
-                    st.push_back(it->second);
-                    break;
-                }
-                case Token::CONST: st.push_back(hex_double(t.value)); break;
-                case Token::NEG:
-                case Token::SQR: {
-                    std::string x = st.back();
-                    st.pop_back();
-                    std::string name = "t" + std::to_string(tmp++);
-                    body += "  const double " + name + " = " +
-                            (t.kind == Token::NEG ? "-" + x : x + " * " + x) + ";\n";
-                    st.push_back(name);
-                    break;
-                }
-                default: {
-                    std::string y = st.back();
-                    st.pop_back();
-                    std::string x = st.back();
-                    st.pop_back();
-                    const char* op = t.kind == Token::ADD ? " + " : t.kind == Token::SUB ? " - "
-                                   : t.kind == Token::MUL ? " * " : " / ";
-                    std::string name = "t" + std::to_string(tmp++);
-                    body += "  const double " + name + " = " + x + op + y + ";\n";
-                    st.push_back(name);
-                }
+    // two elements
+    {
+        std::map<std::tuple<int, int, int>, std::string> pairs;
+        std::string loads, body;
+        auto pair_of = [&](int slot, int di, int dj) -> std::string {
+            auto key = std::make_tuple(slot, di, dj);
+            auto it = pairs.find(key);
+            if (it == pairs.end()) {
+                const std::string name = "p" + std::to_string(pairs.size());
+                loads += "    const sten_pair " + name + " = *reinterpret_cast<const sten_pair*>(" +
+                         address(slot, di, dj) + ");\n";
+                it = pairs.emplace(key, name).first;
             }
+            return it->second;
+        };
+        std::vector<std::string> res[2];
+        for (int el = 0; el < 2; ++el)
+            for (const auto& e : prog.outs)
+                res[el].push_back(emit_expression(
+                    e, [&](int slot, int di, int dj) { return pair_of(slot, di, dj) + (el == 0 ? ".x" : ".y"); },
+                    tmp, body));
+        s += "  if (j + 1 < a.cols) {\n" + loads + body;
+        for (size_t o = 0; o < prog.outs.size(); ++o) {
+            s += "    { sten_pair v; v.x = " + res[0][o] + "; v.y = " + res[1][o] + ";\n";
+            s += "      *reinterpret_cast<sten_pair*>(a.out[" + std::to_string(o) + "] + r * a.ldo[" +
+                 std::to_string(o) + "] + j) = v; }\n";
         }
-        body += "  a.out[" + std::to_string(o) + "][r * a.ldo[" + std::to_string(o) + "] + j] = " + st.back() +
-                ";\n";
+        s += "    return;\n  }\n";
     }
-    s += body;
+    // the last column of an odd-width region
+    {
+        std::map<std::tuple<int, int, int>, std::string> vals;
+        std::string loads, body;
+        auto val_of = [&](int slot, int di, int dj) -> std::string {
+            auto key = std::make_tuple(slot, di, dj);
+            auto it = vals.find(key);
+            if (it == vals.end()) {
+                const std::string name = "l" + std::to_string(vals.size());
+                loads += "    const double " + name + " = *(" + address(slot, di, dj) + ");\n";
+                it = vals.emplace(key, name).first;
+            }
+            return it->second;
+        };
+        std::vector<std::string> res;
+        for (const auto& e : prog.outs) res.push_back(emit_expression(e, val_of, tmp, body));
+        s += "  {\n" + loads + body;
+        for (size_t o = 0; o < prog.outs.size(); ++o)
+            s += "    a.out[" + std::to_string(o) + "][r * a.ldo[" + std::to_string(o) + "] + j] = " + res[o] +
+                 ";\n";
+        s += "  }\n";
+    }
     s += "}\n";
     return s;
 }
@@ -331,8 +389,8 @@ sten_status sten_expr_run(const char* program, const sten_expr_in* ins, int32_t 
     if (program == nullptr || ins == nullptr || outs == nullptr) return STEN_ERR_ARG;
     if (nin < 1 || nin > kExprMaxIn || nout < 1 || nout > kExprMaxOut || rows < 0 || cols < 0) return STEN_ERR_ARG;
     // the kernel forms a block's column indices in 32-bit arithmetic
-    if (rows > INT32_MAX || cols > INT32_MAX - kExprBlock) return STEN_ERR_ARG;
-    const int64_t bpr = (cols + kExprBlock - 1) / kExprBlock;
+    if (rows > INT32_MAX || cols > INT32_MAX - kExprBlock * kExprCols) return STEN_ERR_ARG;
+    const int64_t bpr = (cols + kExprBlock * kExprCols - 1) / (kExprBlock * kExprCols);
     if (rows * bpr > INT32_MAX) return STEN_ERR_ARG;
     // One lock from parsing to the kernel lookup: the prepared program (owned by the cache) stays valid
     // while it is read. HIP calls made under it (pointer queries, compile, module load) call nothing back.

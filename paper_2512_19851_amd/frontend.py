@@ -42,8 +42,8 @@ rectangle -> ``sten_sweep_f64`` on a view; a left-to-right sum of
 ``sten_star_f64`` (fused nodes that read the same array share one launch).
 Every other AST, and every fused group of them, becomes a generated kernel
 (``sten_expr_run``: libsten emits HIP source for the group, compiles it at run
-time and launches one thread per output element), as the paper's backend does
-for all ASTs (Section III-C).
+time and launches one thread per two adjacent output elements), as the paper's
+backend does for all ASTs (Section III-C).
 """
 
 from __future__ import annotations
